@@ -11,23 +11,6 @@
 namespace ss {
 
 // ---------------------------------------------------------------------------
-// XCD-aware block order: consecutive hardware block ids go round-robin over
-// the 8 XCDs, each with its own L2.  Give every XCD a contiguous run of
-// logical tiles so neighbouring tiles (which read overlapping coefficient
-// regions) share an L2.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-    constexpr int NX = 8;
-    const int per = (nblocks + NX - 1) / NX;
-    const int xcd = b % NX, local = b / NX;
-    const int full = nblocks % NX == 0 ? NX : nblocks % NX;  // XCDs that get `per` blocks
-    int t;
-    if (xcd < full) t = xcd * per + local;
-    else t = full * per + (xcd - full) * (per - 1) + local;
-    return t;
-}
-
-// ---------------------------------------------------------------------------
 // Forward: the slab walk of one line.  For every slab j of the dominant axis
 // (one DDA step of the paper's projection algorithm), the candidate bases
 // are those with q_d = j and |q_i - P_i(j)| < h (1 + |r_i|) in the two
@@ -142,94 +125,6 @@ struct RayRec {      // 48 bytes
     int d;
     int pad0, pad1;
 };
-
-struct ViewProj {    // detector coordinates of a world point (FP64 set-up)
-    double d0[3], s[3], du_s[3], dv_s[3], nrm[3];
-    double plane;    // (d0 - s) . nrm  (cone)
-    int kind;
-};
-
-// Continuous pixel coordinates (column, row) of world point X.
-// parallel: X = d0 + alpha du + beta dv + t w ;  cone: the detector point
-// of the line through the source and X.  Returns false when undefined.
-__device__ __forceinline__ bool to_detector(const ViewProj &P, const double X[3], double &col, double &row) {
-    double q[3];
-    if (P.kind == 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) q[k] = X[k] - P.d0[k];
-    } else {
-        double dx[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dx[k] = X[k] - P.s[k];
-        const double den = dx[0] * P.nrm[0] + dx[1] * P.nrm[1] + dx[2] * P.nrm[2];
-        if (!(den * P.plane > 0.0)) return false;  // X on or behind the source plane
-        const double lam = P.plane / den;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) q[k] = P.s[k] + lam * dx[k] - P.d0[k];
-    }
-    col = q[0] * P.du_s[0] + q[1] * P.du_s[1] + q[2] * P.du_s[2];
-    row = q[0] * P.dv_s[0] + q[1] * P.dv_s[1] + q[2] * P.dv_s[2];
-    return true;
-}
-
-// Dual basis: du_s . du = 1, du_s . dv = 0, du_s . m = 0 (m = w or the
-// detector normal), likewise dv_s.
-__device__ __forceinline__ void make_viewproj(const float *__restrict__ e, int kind, ViewProj &P) {
-    double du[3], dv[3], m[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        P.s[k] = e[k];
-        P.d0[k] = e[3 + k];
-        du[k] = e[6 + k];
-        dv[k] = e[9 + k];
-    }
-    P.kind = kind;
-    P.nrm[0] = du[1] * dv[2] - du[2] * dv[1];
-    P.nrm[1] = du[2] * dv[0] - du[0] * dv[2];
-    P.nrm[2] = du[0] * dv[1] - du[1] * dv[0];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) m[k] = kind == 0 ? P.s[k] : P.nrm[k];
-    P.plane = (P.d0[0] - P.s[0]) * P.nrm[0] + (P.d0[1] - P.s[1]) * P.nrm[1] + (P.d0[2] - P.s[2]) * P.nrm[2];
-    // rows of inverse([du dv m]) via cross products
-    double c0[3] = {dv[1] * m[2] - dv[2] * m[1], dv[2] * m[0] - dv[0] * m[2], dv[0] * m[1] - dv[1] * m[0]};
-    double c1[3] = {m[1] * du[2] - m[2] * du[1], m[2] * du[0] - m[0] * du[2], m[0] * du[1] - m[1] * du[0]};
-    const double det = du[0] * c0[0] + du[1] * c0[1] + du[2] * c0[2];
-    const double id = det != 0.0 ? 1.0 / det : 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        P.du_s[k] = c0[k] * id;
-        P.dv_s[k] = c1[k] * id;
-    }
-}
-
-// Pixel rectangle [i0, i1] x [j0, j1] covering every line that meets the
-// box [lo, hi] (whole detector if the projection is undefined).
-__device__ __forceinline__ void box_to_pixels(const ViewProj &P, const double lo[3], const double hi[3], int R,
-                                              int C, int &i0, int &i1, int &j0, int &j1) {
-    double cmin = 1e300, cmax = -1e300, rmin = 1e300, rmax = -1e300;
-    bool ok = true;
-#pragma unroll
-    for (int corner = 0; corner < 8; ++corner) {
-        double X[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) X[k] = ((corner >> k) & 1) ? hi[k] : lo[k];
-        double cc, rr;
-        if (!to_detector(P, X, cc, rr)) ok = false;
-        cmin = fmin(cmin, cc); cmax = fmax(cmax, cc);
-        rmin = fmin(rmin, rr); rmax = fmax(rmax, rr);
-    }
-    if (!ok) { i0 = 0; i1 = C - 1; j0 = 0; j1 = R - 1; return; }
-    const double oc = 0.5 * (C - 1), orow = 0.5 * (R - 1);
-    const double fi0 = floor(cmin + oc) - 1.0, fi1 = ceil(cmax + oc) + 1.0;
-    const double fj0 = floor(rmin + orow) - 1.0, fj1 = ceil(rmax + orow) + 1.0;
-    if (!(fi1 >= 0.0 && fj1 >= 0.0 && fi0 <= (double)(C - 1) && fj0 <= (double)(R - 1))) {
-        i0 = 0; i1 = -1; j0 = 0; j1 = -1;  // empty (also catches NaN)
-        return;
-    }
-    // clamped in FP64 before converting
-    i0 = (int)fmax(fi0, 0.0); i1 = (int)fmin(fi1, (double)(C - 1));
-    j0 = (int)fmax(fj0, 0.0); j1 = (int)fmin(fj1, (double)(R - 1));
-}
 
 template <int n>
 __device__ __forceinline__ void fill_ray(RayRec &rec, const float *__restrict__ e, int kind, int R, int C, int j,

@@ -20,6 +20,7 @@
 
 #include "splinesplat.h"
 #include "ss_math.hpp"
+#include "ss_traverse.hpp"
 
 namespace ss {
 
