@@ -194,7 +194,7 @@ def smooth_field(dims, sigma: float = 4.0, seed: int = 6) -> np.ndarray:
     f1 = np.fft.rfftfreq(N1)[None, None, :]
     k2 = (2 * np.pi) ** 2 * (f1 * f1 + f2 * f2 + f3 * f3)
     G *= np.exp(-0.5 * sigma * sigma * k2)
-    out = np.fft.irfftn(G, s=(N3, N2, N1)).astype(np.float32)
+    out = np.fft.irfftn(G, s=(N3, N2, N1), axes=(0, 1, 2)).astype(np.float32)
     out -= out.mean(dtype=np.float64)
     out /= out.std(dtype=np.float64)
     return out

@@ -1,0 +1,100 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (one call over all views), on sampled outputs the FP64 oracle
+computes one by one: 16,384 lines (seed 7) and 4,096 coefficients (seed 8).
+
+parallel_128: 128^3, ellipsoids + noise, 240 parallel views, 192^2 detector.
+cone_256:     256^3, ellipsoids, 360 cone views, 384^2 detector.
+cone_512:     512^3 smooth field, one batch of 32 of its 720 cone views.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2511_11078_amd import configs, synth
+from paper_2511_11078_amd.ops import Context, default_weights
+
+from gpu_helpers import rel_l2, say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL_QUAD = 1e-5
+TOL_MLP = 1e-2
+_VOLUMES = {}
+
+
+def _volume(wl):
+    if wl.name not in _VOLUMES:
+        _VOLUMES[wl.name] = wl.volume()
+    return _VOLUMES[wl.name]
+
+
+def _check(wl_name, form, n_rays=16384, n_coefs=4096, views=None):
+    wl = configs.get(wl_name)
+    geom = wl.geometry() if views is None else wl.geometry().subset_views(*views)
+    dims = wl.dims
+    c_np = _volume(wl)
+    ctx = Context(wl.degree, form, 0)
+    c = to_gpu(c_np)
+    y = ctx.project(c, geom)
+    b = ctx.backproject(y, geom, dims)
+    torch.cuda.synchronize()
+    rays = synth.sample_indices(geom.n_rays, n_rays, seed=7)
+    coefs = synth.sample_indices(int(np.prod(dims)), n_coefs, seed=8)
+    y_np = to_np(y)
+    ef = rel_l2(y_np.ravel()[rays], oracle.project(c_np, geom, wl.degree, rays=rays))
+    eb = rel_l2(to_np(b).ravel()[coefs], oracle.backproject_subset(y_np, geom, dims, wl.degree, coefs=coefs))
+    say(f"  {wl_name} {form}: forward rel-L2 {ef:.3e}, adjoint rel-L2 {eb:.3e}")
+    ctx.close()
+    return ef, eb
+
+
+def test_parallel_128_quad():
+    say("parallel_128 quad")
+    ef, eb = _check("parallel_128", "quad")
+    assert ef <= TOL_QUAD and eb <= TOL_QUAD
+
+
+def test_parallel_128_dot_test():
+    say("parallel_128 dot test")
+    wl = configs.get("parallel_128")
+    geom = wl.geometry()
+    ctx = Context(3, "quad", 0)
+    rng = np.random.default_rng(5)
+    x = to_gpu(rng.standard_normal(wl.dims[::-1]).astype(np.float32))
+    y = to_gpu(rng.standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32))
+    Ax = ctx.project(x, geom)
+    Aty = ctx.backproject(y, geom, wl.dims)
+    lhs = float((Ax.double() * y.double()).sum())
+    rhs = float((x.double() * Aty.double()).sum())
+    rel = abs(lhs - rhs) / (float(Ax.double().norm()) * float(y.double().norm()))
+    say(f"  dot-test relative mismatch {rel:.3e}")
+    assert rel <= 1e-5
+
+
+def test_cone_256_quad():
+    say("cone_256 quad")
+    ef, eb = _check("cone_256", "quad", n_coefs=1024)
+    assert ef <= TOL_QUAD and eb <= TOL_QUAD
+
+
+@pytest.mark.skipif(not os.path.exists(default_weights(3)), reason="no trained network weights")
+def test_parallel_128_mlp():
+    say("parallel_128 mlp")
+    ef, eb = _check("parallel_128", "mlp", n_coefs=1024)
+    assert ef <= TOL_MLP and eb <= 3 * TOL_MLP
+
+
+@pytest.mark.skipif(not os.path.exists(default_weights(3)), reason="no trained network weights")
+def test_cone_512_one_batch_mlp():
+    say("cone_512, views 0..31, mlp")
+    ef, eb = _check("cone_512", "mlp", n_rays=4096, n_coefs=256, views=(0, 32))
+    assert ef <= TOL_MLP and eb <= 3 * TOL_MLP
+
+
+def test_cone_512_one_batch_quad():
+    say("cone_512, views 32..63, quad")
+    ef, eb = _check("cone_512", "quad", n_rays=4096, n_coefs=256, views=(32, 64))
+    assert ef <= 3e-5 and eb <= 3e-5
