@@ -71,11 +71,26 @@ __device__ __forceinline__ void walk_line(const LineD &L, const int N[3], Visit 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Forward, quadrature form: cell walk.  The footprint of a basis is the sum,
+// over the knot cells its support spans, of the Gauss-Legendre integral of
+// its (polynomial) restriction to the line inside the cell.  Walking the
+// line cell by cell through the knot lattice (Amanatides-Woo stepping over
+// the support-padded box) and adding, for every cell, c_q times that
+// per-cell integral for each of the (n+1)^3 bases whose support covers the
+// cell visits every (line, basis) pair of eq. (4) exactly once, through the
+// same Gauss-Legendre terms as the slab-by-slab per-basis sum, evaluated
+// with the node positions and per-axis weights shared by the (n+1)^3 bases.
+// ---------------------------------------------------------------------------
 template <int n>
 __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ c, int N0, int N1, int N2,
                                                       const float *__restrict__ geom, int kind, int V, int R,
                                                       int C, float *__restrict__ y) {
-    // block = 16 x 16 pixels of one view; each wave an 8 x 8 sub-tile
+    using Rule = GLRule<Degree<n>::m>;
+    constexpr int NB = n + 1;
+    constexpr double h = (double)Degree<n>::h;
+    constexpr double kap = (double)Degree<n>::kap;
+    constexpr int qoff = CellBasis<n>::qoff;
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
     const int nblocks = V * tR * tC;
     const int b = xcd_remap(blockIdx.x, nblocks);
@@ -85,23 +100,128 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
     const int i = (rem % tC) * 16 + (wave & 1) * 8 + (lane & 7);
     if (v >= V || j >= R || i >= C) return;
     const int N[3] = {N0, N1, N2};
-    const int64_t strides[3] = {1, (int64_t)N0, (int64_t)N0 * N1};
     const double centre[3] = {0.0, 0.0, 0.0};
     const LineD L = make_line(geom + 12 * v, kind, R, C, j, i, centre);
     float acc = 0.0f;
     if (L.ok) {
-        walk_line<n>(L, N, [&](const Slopes &S, float u1, float u2, int d, int jj, int i1, int q1, int i2, int q2) {
-            const float f = footprint_slab<n>(S, u1, u2);
-            if (f != 0.0f) {
-                const int64_t idx = (int64_t)jj * pick3(strides, d) + (int64_t)q1 * pick3(strides, i1) +
-                                    (int64_t)q2 * pick3(strides, i2);
-                acc = fmaf(c[idx], f, acc);
+        // index coordinates z = x - o, o = -(N - 1)/2
+        double z0[3], t0 = -1e300, t1 = 1e300;
+        bool hit = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            z0[k] = L.a[k] + 0.5 * (double)(N[k] - 1);
+            const double lo = -h, hi = (double)(N[k] - 1) + h;
+            if (L.w[k] == 0.0) {
+                if (!(z0[k] > lo && z0[k] < hi)) hit = false;
+                // degree 0: the support of beta^0 is open, so a line lying in
+                // a face plane between two voxels meets neither
+                if (n == 0 && z0[k] - kap == floor(z0[k] - kap)) hit = false;
+            } else {
+                const double ta = (lo - z0[k]) / L.w[k], tb = (hi - z0[k]) / L.w[k];
+                t0 = fmax(t0, fmin(ta, tb));
+                t1 = fmin(t1, fmax(ta, tb));
             }
-        });
-        // 1 / |w_d| converts the slab-form integral into the line integral
-        int d, i1, i2;
-        dominant_axis(L.w, d, i1, i2);
-        acc *= (float)(1.0 / fabs(pick3(L.w, d)));
+        }
+        if (hit && t0 < t1) {
+            // DDA state per axis
+            int m[3], stp[3];
+            double tmax[3], tdel[3];
+            // a point just past the entry (the entry lies on a knot plane)
+            const double tm0 = t0 + fmin(1e-6, 0.5 * (t1 - t0));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double zs = fma(tm0, L.w[k], z0[k]) - kap;
+                m[k] = (int)floor(fmin(fmax(zs, -8.0), (double)N[k] + 8.0));
+                if (L.w[k] > 0.0) {
+                    stp[k] = 1;
+                    tdel[k] = 1.0 / L.w[k];
+                    tmax[k] = ((double)(m[k] + 1) + kap - z0[k]) / L.w[k];
+                } else if (L.w[k] < 0.0) {
+                    stp[k] = -1;
+                    tdel[k] = -1.0 / L.w[k];
+                    tmax[k] = ((double)m[k] + kap - z0[k]) / L.w[k];
+                } else {
+                    stp[k] = 0;
+                    tdel[k] = 0.0;
+                    tmax[k] = 1e300;
+                }
+            }
+            const int64_t s1 = N0, s2 = (int64_t)N0 * N1;
+            double tc = t0;
+            // every step moves one axis to its next knot plane: the walk ends
+            // after at most sum_k (N_k + 2h + 2) steps
+            while (tc < t1) {
+                int ax = 0;
+                double tn = tmax[0];
+                if (tmax[1] < tn) { tn = tmax[1]; ax = 1; }
+                if (tmax[2] < tn) { tn = tmax[2]; ax = 2; }
+                tn = fmin(tn, t1);
+                if (tn > tc) {
+                    const double mid = 0.5 * (tc + tn), half = 0.5 * (tn - tc);
+                    float lc[3], dl[3];
+                    int q0[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        lc[k] = (float)(fma(mid, L.w[k], z0[k]) - ((double)m[k] + kap));
+                        dl[k] = (float)(half * L.w[k]);
+                        q0[k] = m[k] + qoff;
+                    }
+                    // coefficient block (zero outside the volume)
+                    float cb[NB][NB][NB];
+                    const bool inner = q0[0] >= 0 && q0[0] + n < N0 && q0[1] >= 0 && q0[1] + n < N1 &&
+                                       q0[2] >= 0 && q0[2] + n < N2;
+                    if (inner) {
+                        const float *base = c + (int64_t)q0[2] * s2 + (int64_t)q0[1] * s1 + q0[0];
+#pragma unroll
+                        for (int a3 = 0; a3 < NB; ++a3)
+#pragma unroll
+                            for (int a2 = 0; a2 < NB; ++a2)
+#pragma unroll
+                                for (int a1 = 0; a1 < NB; ++a1) cb[a3][a2][a1] = base[a3 * s2 + a2 * s1 + a1];
+                    } else {
+#pragma unroll
+                        for (int a3 = 0; a3 < NB; ++a3)
+#pragma unroll
+                            for (int a2 = 0; a2 < NB; ++a2)
+#pragma unroll
+                                for (int a1 = 0; a1 < NB; ++a1) {
+                                    const int k1 = q0[0] + a1, k2 = q0[1] + a2, k3 = q0[2] + a3;
+                                    const bool ok = k1 >= 0 && k1 < N0 && k2 >= 0 && k2 < N1 && k3 >= 0 && k3 < N2;
+                                    cb[a3][a2][a1] = ok ? c[(int64_t)k3 * s2 + (int64_t)k2 * s1 + k1] : 0.0f;
+                                }
+                    }
+                    float seg = 0.0f;
+#pragma unroll
+                    for (int l = 0; l < Rule::m; ++l) {
+                        const float xi = Rule::x(l);
+                        float w1[NB], w2[NB], w3[NB];
+                        cell_weights<n>(fmaf(dl[0], xi, lc[0]), w1);
+                        cell_weights<n>(fmaf(dl[1], xi, lc[1]), w2);
+                        cell_weights<n>(fmaf(dl[2], xi, lc[2]), w3);
+                        float f = 0.0f;
+#pragma unroll
+                        for (int a3 = 0; a3 < NB; ++a3) {
+                            float g = 0.0f;
+#pragma unroll
+                            for (int a2 = 0; a2 < NB; ++a2) {
+                                float r = 0.0f;
+#pragma unroll
+                                for (int a1 = 0; a1 < NB; ++a1) r = fmaf(w1[a1], cb[a3][a2][a1], r);
+                                g = fmaf(w2[a2], r, g);
+                            }
+                            f = fmaf(w3[a3], g, f);
+                        }
+                        seg = fmaf(Rule::w(l), f, seg);
+                    }
+                    acc = fmaf((float)half, seg, acc);
+                }
+                tc = fmax(tc, tn);
+                // advance the axis whose plane was reached
+                if (ax == 0) { m[0] += stp[0]; tmax[0] += tdel[0]; }
+                else if (ax == 1) { m[1] += stp[1]; tmax[1] += tdel[1]; }
+                else { m[2] += stp[2]; tmax[2] += tdel[2]; }
+            }
+        }
     }
     y[((int64_t)v * R + j) * C + i] = acc;
 }

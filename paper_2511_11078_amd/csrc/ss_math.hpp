@@ -127,6 +127,41 @@ __device__ __forceinline__ float bspline(float z) {
 }
 
 // ---------------------------------------------------------------------------
+// B-spline weights inside one knot cell.  Along an axis the knot planes sit
+// at kap + m (index units); inside the cell [kap + m, kap + m + 1] exactly
+// n + 1 bases are non-zero, q = m + qoff .. m + qoff + n, and with the local
+// coordinate t in [0, 1) their values are the uniform B-spline blending
+// polynomials below (wt[a] is the weight of basis m + qoff + a).
+// ---------------------------------------------------------------------------
+template <int n> struct CellBasis;
+template <> struct CellBasis<0> { static constexpr int qoff = 1; };
+template <> struct CellBasis<1> { static constexpr int qoff = 0; };
+template <> struct CellBasis<2> { static constexpr int qoff = 0; };
+template <> struct CellBasis<3> { static constexpr int qoff = -1; };
+
+template <int n>
+__device__ __forceinline__ void cell_weights(float t, float wt[n + 1]) {
+    if constexpr (n == 0) {
+        wt[0] = 1.0f;
+    } else if constexpr (n == 1) {
+        wt[0] = 1.0f - t;
+        wt[1] = t;
+    } else if constexpr (n == 2) {
+        const float s = 1.0f - t;
+        wt[0] = 0.5f * s * s;
+        wt[1] = fmaf(t, s, 0.5f);            // 1/2 + t - t^2
+        wt[2] = 0.5f * t * t;
+    } else {
+        const float s = 1.0f - t, t2 = t * t, s2 = s * s;
+        const float k6 = 1.0f / 6.0f;
+        wt[0] = k6 * s2 * s;                               // (1-t)^3 / 6
+        wt[3] = k6 * t2 * t;                               // t^3 / 6
+        wt[1] = fmaf(t2, fmaf(0.5f, t, -1.0f), 2.0f / 3.0f);  // 2/3 - t^2 + t^3/2
+        wt[2] = fmaf(s2, fmaf(0.5f, s, -1.0f), 2.0f / 3.0f);  // same in 1 - t
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-line data of the slab form.  ir_i = 1 / r_i, or 0 when r_i == 0.
 // ---------------------------------------------------------------------------
 struct Slopes {
