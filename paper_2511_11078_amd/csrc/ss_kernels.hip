@@ -285,9 +285,11 @@ __global__ void __launch_bounds__(256) backproject_kernel(const float *__restric
                               o[2] + bz * BZ + 0.5 * (BZ - 1)};
     const float xq[3] = {(float)(o[0] + k0 - centre[0]), (float)(o[1] + k1 - centre[1]),
                          (float)(o[2] + k2 - centre[2])};
-    float acc = 0.0f;
+    // FP32 sums within a view, accumulated across views in FP64
+    double acc = 0.0;
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
+        float part = 0.0f;
         if (tid == 0) {
             make_viewproj(e, kind, vp);
             double lo[3], hi[3];
@@ -349,15 +351,16 @@ __global__ void __launch_bounds__(256) backproject_kernel(const float *__restric
                             Slopes S;
                             S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
                             const float f = footprint_slab<n>(S, u1, u2);
-                            if (f != 0.0f) acc = fmaf(rr.y * rr.len, f, acc);
+                            if (f != 0.0f) part = fmaf(rr.y * rr.len, f, part);
                         }
                     }
                 }
             }
         }
         __syncthreads();
+        acc += (double)part;
     }
-    if (mine) c[((int64_t)k2 * N1 + k1) * N0 + k0] = acc;
+    if (mine) c[((int64_t)k2 * N1 + k1) * N0 + k0] = (float)acc;
 }
 
 // ---------------------------------------------------------------------------
