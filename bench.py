@@ -15,7 +15,11 @@ measured with HIP events on its stream), the relative L2 error against the
 FP64 oracle on 16,384 sampled lines (seed 7) and 4,096 sampled coefficients
 (seed 8), and the oracle itself timed on the host as the CPU baseline.
 
-    python bench.py [--steps K] [--warmup W] [--form quad|mlp] [--both-forms]
+    python bench.py [--steps K] [--warmup W] [--form quad|mlp] [--one-form]
+
+By default one extra, separately timed step of the other footprint form
+(the network form when its weights are present) reports the network vs
+quadrature speed-up and the network form's error.
 """
 from __future__ import annotations
 
@@ -54,14 +58,26 @@ def quad_flops_per_pair(n: int, segs_per_pair: float) -> float:
 MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16 + layer 1 + output
 
 
+def cell_flops(n: int) -> float:
+    """Algorithmic FP32 work of one knot cell of the forward walk: at each of
+    the m Gauss-Legendre nodes, the n+1 blending weights of three axes
+    (2n + 3 operations each), the contraction with the (n+1)^3 coefficient
+    block ((n+1)^3 + (n+1)^2 + (n+1) FMA) and 4 operations for the node map
+    and the weighted sum; 2 flops per operation."""
+    m = GL_ORDER[n]
+    nb = n + 1
+    return 2.0 * m * (3 * (2 * n + 3) + nb ** 3 + nb ** 2 + nb + 4)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", choices=["quad", "mlp"], default="quad")
-    ap.add_argument("--both-forms", action="store_true",
-                    help="also time the other footprint form (one step) for the speed-up")
+    ap.add_argument("--form", choices=["quad", "mlp"], default="quad",
+                    help="footprint form of the timed steps")
+    ap.add_argument("--one-form", action="store_true",
+                    help="skip the one extra step of the other footprint form (speed-up report)")
     ap.add_argument("--workload", default="cone_256")
     ap.add_argument("--no-oracle", action="store_true", help="skip parity and CPU baseline (profiling runs)")
     args = ap.parse_args()
@@ -93,7 +109,7 @@ def main():
     b = torch.empty_like(c)
 
     forms = [args.form]
-    if args.both_forms:
+    if not args.one_form:
         other = "mlp" if args.form == "quad" else "quad"
         if other == "quad" or os.path.exists(default_weights(n)):
             forms.append(other)
@@ -103,7 +119,7 @@ def main():
         ctx = Context(n, form, 0)
         stream = torch.cuda.current_stream(dev)
         steps = args.steps if fi == 0 else 1
-        warm = args.warmup if fi == 0 else 1
+        warm = args.warmup if fi == 0 else 0
         for k in range(warm):
             ctx.project(c, geom, y)
             ctx.backproject(y, geom, dims, b)
@@ -135,8 +151,6 @@ def main():
         cs = synth.sample_indices(int(np.prod(dims)), 4096, seed=8)
         results[form]["y_sample"] = y.reshape(-1)[torch.from_numpy(ys).to(dev)].cpu().numpy()
         results[form]["b_sample"] = b.reshape(-1)[torch.from_numpy(cs).to(dev)].cpu().numpy()
-        if fi == 0:
-            y_first = y.clone()
         ctx.close()
 
     main_form = forms[0]
@@ -177,33 +191,44 @@ def main():
                 entry["adjoint_rel_l2"] = ra
             rel[form] = entry
         out["rel_l2_vs_oracle"] = rel[main_form]
-        # algorithmic work: pairs and polynomial segments per line (oracle counts)
+        # algorithmic work (oracle counts on 4,096 of the sampled lines):
+        # (line, basis) pairs and their footprint segments, and knot cells per line
         cnt_rays = ys[:4096]
         pairs, segs = oracle.counts(dims, geom, n, rays=cnt_rays)
+        cells = oracle.direct_counts(dims, geom, n, rays=cnt_rays)
         pairs_per_ray = float(pairs.mean())
         segs_per_pair = float(segs.sum() / max(pairs.sum(), 1))
+        cells_per_ray = float(cells.mean())
         total_pairs = pairs_per_ray * R
-        # roofline of the dominant kernel of the main form
-        kern_ms = max(r0["fwd_ms"], r0["adj_ms"])
-        kern_name = "project" if r0["fwd_ms"] >= r0["adj_ms"] else "backproject"
+        kernels = []
         if main_form == "quad":
-            flops = total_pairs * quad_flops_per_pair(n, segs_per_pair)
-            ach = flops / (kern_ms / 1e3) / 1e12
-            out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                               "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                               "kernel": f"{kern_name}_kernel<{n}>", "kernel_ms": kern_ms,
-                               "work": {"pairs_per_launch": total_pairs, "pairs_per_ray": pairs_per_ray,
-                                        "segments_per_pair": segs_per_pair,
-                                        "flops_per_pair": quad_flops_per_pair(n, segs_per_pair),
-                                        "count_sample_rays": int(cnt_rays.size)}}
+            fl_f = R * cells_per_ray * cell_flops(n)
+            fl_a = total_pairs * quad_flops_per_pair(n, segs_per_pair)
+            for name, ms, fl, unit in ((f"project_kernel<{n}> (knot-cell walk)", r0["fwd_ms"], fl_f,
+                                        f"{cell_flops(n):.0f} flop per cell x {cells_per_ray:.1f} cells/line"),
+                                       (f"backproject_kernel<{n}> (per-pair brick gather)", r0["adj_ms"], fl_a,
+                                        f"{quad_flops_per_pair(n, segs_per_pair):.0f} flop per pair x "
+                                        f"{pairs_per_ray:.0f} pairs/line")):
+                ach = fl / (ms / 1e3) / 1e12
+                kernels.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
+                                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit})
         else:
-            flops = total_pairs * MLP_FLOPS_PER_PAIR
-            ach = flops / (kern_ms / 1e3) / 1e12
-            out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
-                               "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS, "traffic": None,
-                               "kernel": f"{kern_name}_mlp_kernel<{n}>", "kernel_ms": kern_ms,
-                               "work": {"pairs_per_launch": total_pairs, "pairs_per_ray": pairs_per_ray,
-                                        "mfma_flops_per_pair": MLP_FLOPS_PER_PAIR}}
+            fl = total_pairs * MLP_FLOPS_PER_PAIR
+            for name, ms in ((f"project_mlp_kernel<{n}>", r0["fwd_ms"]), (f"backproject_mlp_kernel<{n}>", r0["adj_ms"])):
+                ach = fl / (ms / 1e3) / 1e12
+                kernels.append({"kernel": name, "ms": ms, "bound": "mfma", "achieved": ach,
+                                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                "frac": ach / PEAK_BF16_MFMA_TFLOPS,
+                                "work": f"{MLP_FLOPS_PER_PAIR:.0f} matrix-core flop per pair x {pairs_per_ray:.0f} pairs/line"})
+        dom = max(kernels, key=lambda k: k["ms"])
+        out["roofline"] = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                           "unit": dom["unit"], "frac": dom["frac"], "traffic": None, "kernel": dom["kernel"],
+                           "kernel_ms": dom["ms"], "work": dom["work"]}
+        out["kernels"] = kernels
+        out["work_counts"] = {"sample_lines": int(cnt_rays.size), "pairs_per_line": pairs_per_ray,
+                              "segments_per_pair": segs_per_pair, "cells_per_line": cells_per_ray,
+                              "pairs_per_application": total_pairs}
         # CPU baseline: the oracle as it stands, extrapolated from its samples
         t_fwd_all = t_of * R / ys.size
         t_adj_all = t_ob * float(np.prod(dims)) / cs_small.size

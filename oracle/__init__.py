@@ -61,6 +61,7 @@ def _load():
     lib.or_project.argtypes = [I, P, P] + geo + [P, L, P]
     lib.or_project_basis_sum.argtypes = [I, P, P] + geo + [P, L, P]
     lib.or_counts.argtypes = [I, P] + geo + [P, L, P, P]
+    lib.or_direct_counts.argtypes = [I, P] + geo + [P, L, P]
     lib.or_backproject_subset.argtypes = [I, P, P] + geo + [P, L, P]
     lib.or_dense_matrix.argtypes = [I, P] + geo + [P, L, P]
     lib.or_num_threads.restype = I
@@ -190,6 +191,21 @@ def counts(dims, geom, n: int = 3, rays=None):
     if rc:
         raise ValueError("oracle counts failed")
     return pairs, segs
+
+
+def direct_counts(dims, geom, n: int = 3, rays=None):
+    """O9: per-ray number of polynomial segments of the direct integral (the
+    knot cells of the support-padded box each line passes through)."""
+    dims = _dims(dims)
+    vecs, g = _geom_args(geom)
+    total = g[1] * g[2] * g[3]
+    idx, cnt = _idx(rays, total)
+    segs = np.empty(cnt, dtype=np.int64)
+    rc = _load().or_direct_counts(n, _ptr(dims), *g, _ptr(vecs), None if idx is None else _ptr(idx), cnt,
+                                  _ptr(segs))
+    if rc:
+        raise ValueError("oracle direct counts failed")
+    return segs
 
 
 def backproject_subset(y, geom, dims, n: int = 3, coefs=None) -> np.ndarray:

@@ -32,7 +32,7 @@
  *         O5 or_project_basis_sum          sum_k c_k * O4 (eq. (4))
  *         O6 or_backproject_subset         voxel-driven transpose of eq. (7)
  *         O7 or_dense_matrix               eq. (7) as a dense matrix
- *         O9 or_counts                     pairs / segments per ray
+ *         O9 or_counts, or_direct_counts   pairs / segments per ray
  */
 #include <math.h>
 #include <stdint.h>
@@ -358,6 +358,40 @@ static double ray_direct(int n, const float *c, const int64_t N[3], const double
     return ks_val(&acc);
 }
 
+/* Number of non-empty polynomial segments of the direct integral: the
+ * knot cells of the padded box the line passes through. */
+static int64_t ray_direct_segments(int n, const int64_t N[3], const double a[3], const double w[3],
+                                   double *T)
+{
+    double h = 0.5 * (n + 1), o[3], lo[3], hi[3];
+    for (int i = 0; i < 3; ++i) {
+        o[i] = -0.5 * (double)(N[i] - 1);
+        lo[i] = o[i] - h;
+        hi[i] = o[i] + (double)(N[i] - 1) + h;
+    }
+    double t0, t1;
+    if (!clip_box(a, w, lo, hi, &t0, &t1)) return 0;
+    double kap = (n & 1) ? 0.0 : 0.5;
+    int64_t nt = 0;
+    T[nt++] = t0;
+    T[nt++] = t1;
+    for (int i = 0; i < 3; ++i) {
+        if (w[i] == 0.0) continue;
+        double xa = a[i] + t0 * w[i], xb = a[i] + t1 * w[i];
+        double xl = fmin(xa, xb), xh = fmax(xa, xb);
+        int64_t m0 = (int64_t)floor(xl - o[i] - kap) - 1, m1 = (int64_t)ceil(xh - o[i] - kap) + 1;
+        for (int64_t mm = m0; mm <= m1; ++mm) {
+            double t = (o[i] + kap + (double)mm - a[i]) / w[i];
+            if (t > t0 && t < t1) T[nt++] = t;
+        }
+    }
+    qsort(T, nt, sizeof(double), cmp_double);
+    int64_t segs = 0;
+    for (int64_t s = 0; s + 1 < nt; ++s)
+        if (T[s + 1] > T[s]) ++segs;
+    return segs;
+}
+
 static int check_args(int n, const int64_t N[3], int kind, int V, int R, int C)
 {
     if (n < 0 || n > 3) return 1;
@@ -518,6 +552,29 @@ int or_counts(int n, const int64_t N[3], int kind, int V, int R, int C, const fl
         enumerate_pairs(n, N, a, w, bsum_visit, &b);
         pairs[k] = b.pairs;
         segs[k] = b.segs;
+    }
+    return bad;
+}
+
+int or_direct_counts(int n, const int64_t N[3], int kind, int V, int R, int C, const float *vecs,
+                     const int64_t *rays, int64_t nrays, int64_t *segs)
+{
+    if (check_args(n, N, kind, V, R, C)) return 1;
+    geom_t g = {kind, V, R, C, vecs};
+    int64_t cap = 2 + 3 * (N[0] + N[1] + N[2]) + 32;
+    int bad = 0;
+#pragma omp parallel
+    {
+        double *T = (double *)malloc(sizeof(double) * cap);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < nrays; ++k) {
+            double a[3], w[3];
+            int64_t r = rays ? rays[k] : k;
+            segs[k] = 0;
+            if (make_ray(&g, r, a, w)) { bad = 1; continue; }
+            segs[k] = ray_direct_segments(n, N, a, w, T);
+        }
+        free(T);
     }
     return bad;
 }

@@ -267,3 +267,39 @@ def test_cgls_matches_textbook_cg_and_lstsq():
     x_long, _ = oracle.cgls(lambda v: A @ v, lambda r: A.T @ r, y, 400)
     x_ls = np.linalg.lstsq(A, y, rcond=None)[0]
     np.testing.assert_allclose(A @ x_long, A @ x_ls, atol=1e-8 * np.abs(A @ x_ls).max())
+
+
+@pytest.mark.parametrize("n", [0, 2, 3])
+def test_direct_segment_counts(n):
+    """An axis-aligned line inside the volume crosses every knot cell of the
+    padded box along its axis: N + n + 1 cells (the padded box spans
+    N - 1 + 2h = N + n units, bounded by knot planes); an oblique line
+    crosses one more cell per knot plane of each other axis."""
+    dims = (6, 7, 8)
+    vecs = np.zeros((2, 12))
+    vecs[0, 0:3] = [0.0, 0.0, 1.0]
+    vecs[0, 3:6] = [0.13, -0.21, 0.0]
+    vecs[0, 6] = 1.0
+    vecs[0, 10] = 1.0
+    w = np.array([0.1, 0.05, 1.0])
+    vecs[1, 0:3] = w / np.linalg.norm(w)
+    vecs[1, 3:6] = [0.13, -0.21, 0.0]
+    vecs[1, 6] = 1.0
+    vecs[1, 10] = 1.0
+    geom = synth.Geometry("parallel", 2, 1, 1, vecs.astype(np.float32))
+    segs = oracle.direct_counts(dims, geom, n)
+    assert segs[0] == dims[2] + n
+    a, ww = oracle.make_rays(geom)
+    h = 0.5 * (n + 1)
+    kap = 0.0 if n % 2 else 0.5
+    # planes crossed by the oblique line inside the padded box
+    o = -0.5 * (np.array(dims) - 1)
+    lo, hi = o - h, o + np.array(dims) - 1 + h
+    t = [(lo[i] - a[1][i]) / ww[1][i] for i in range(3)] + [(hi[i] - a[1][i]) / ww[1][i] for i in range(3)]
+    t0 = max(min(t[i], t[i + 3]) for i in range(3))
+    t1 = min(max(t[i], t[i + 3]) for i in range(3))
+    crossings = 0
+    for i in range(3):
+        z = sorted([a[1][i] + t0 * ww[1][i] - o[i] - kap, a[1][i] + t1 * ww[1][i] - o[i] - kap])
+        crossings += int(np.ceil(z[1]) - np.floor(z[0]) - 1)
+    assert segs[1] == crossings + 1
