@@ -197,6 +197,8 @@ __device__ __forceinline__ float mlp_tile(const MlpImage &W, float f0, float f1,
 // Both tiles of a wave: each lane gets the value of its own pair.
 __device__ __forceinline__ float mlp_wave(const MlpImage &W, const float f[5]) {
     const int lane = threadIdx.x & 63;
+    // the two tiles are independent: the scheduler interleaves one tile's
+    // matrix-core work with the other's SiLU
     const float ra = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 0);
     const float rb = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 32);
     return lane < 32 ? ra : rb;
@@ -322,8 +324,10 @@ __device__ __forceinline__ void walk_init(Walk<n> &W, const LineD &L, const int 
     if (W.j <= W.j1) W.window();
 }
 
+// two workgroups (eight waves) per CU: one wave's matrix-core layers overlap
+// another's SiLU
 template <int n>
-__global__ void __launch_bounds__(256) project_mlp_kernel(const float *__restrict__ c, int N0, int N1, int N2,
+__global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__restrict__ c, int N0, int N1, int N2,
                                                           const float *__restrict__ geom, int kind, int V, int R,
                                                           int C, const MlpImage *__restrict__ img,
                                                           float *__restrict__ y) {
@@ -426,7 +430,7 @@ __device__ __forceinline__ void fill_ray_m(RayRecM &rec, const float *__restrict
 }
 
 template <int n>
-__global__ void __launch_bounds__(256) backproject_mlp_kernel(const float *__restrict__ y, int N0, int N1, int N2,
+__global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__restrict__ y, int N0, int N1, int N2,
                                                               const float *__restrict__ geom, int kind, int V,
                                                               int R, int C, const MlpImage *__restrict__ img,
                                                               float *__restrict__ c) {
