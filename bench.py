@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--one-form", action="store_true",
                     help="skip the one extra step of the other footprint form (speed-up report)")
     ap.add_argument("--workload", default="cone_256")
+    ap.add_argument("--degree", type=int, default=None,
+                    help="override the workload's B-spline degree (0 = voxel basis, 2 = quadratic)")
     ap.add_argument("--no-oracle", action="store_true", help="skip parity and CPU baseline (profiling runs)")
     args = ap.parse_args()
 
@@ -95,7 +97,7 @@ def main():
 
     wl = configs.get(args.workload)
     dims = wl.dims
-    n = wl.degree
+    n = wl.degree if args.degree is None else args.degree
     geom = wl.geometry()
     R = geom.n_rays
     dev = torch.device("cuda", 0)
@@ -111,7 +113,7 @@ def main():
     forms = [args.form]
     if not args.one_form:
         other = "mlp" if args.form == "quad" else "quad"
-        if other == "quad" or os.path.exists(default_weights(n)):
+        if other == "quad" or (n > 0 and os.path.exists(default_weights(n))):
             forms.append(other)
 
     results = {}

@@ -140,7 +140,7 @@ def _random_rotation(rng) -> np.ndarray:
     ])
 
 
-def ellipsoid_params(n_ell: int = 6, seed: int = 0):
+def ellipsoid_params(n_ell: int = 6, seed: int = 0, centre_radius: float = 0.5, max_axis: float = 0.5):
     """Random ellipsoids in normalised coordinates [-1, 1]^3: centre uniform in
     the ball of radius 0.5, semi-axes U(0.1, 0.5), uniform random rotation,
     density U(0, 1)."""
@@ -148,24 +148,24 @@ def ellipsoid_params(n_ell: int = 6, seed: int = 0):
     out = []
     for _ in range(n_ell):
         while True:
-            cen = rng.uniform(-0.5, 0.5, 3)
-            if np.linalg.norm(cen) <= 0.5:
+            cen = rng.uniform(-centre_radius, centre_radius, 3)
+            if np.linalg.norm(cen) <= centre_radius:
                 break
-        axes = rng.uniform(0.1, 0.5, 3)
+        axes = rng.uniform(0.1, max_axis, 3)
         rot = _random_rotation(rng)
         rho = rng.uniform(0.0, 1.0)
         out.append((cen, axes, rot, rho))
     return out
 
 
-def ellipsoid_phantom(dims, n_ell: int = 6, seed: int = 0) -> np.ndarray:
+def ellipsoid_phantom(dims, n_ell: int = 6, seed: int = 0, params=None) -> np.ndarray:
     """c_k = sum_e rho_e [xi_k in E_e], xi = x / ((N - 1)/2) per axis; the same
     normalised parameters give 'the same phantom' at every size."""
     N1, N2, N3 = (int(d) for d in dims)
     ax = [(np.arange(n, dtype=np.float64) - 0.5 * (n - 1)) / max(0.5 * (n - 1), 0.5)
           for n in (N1, N2, N3)]
     c = np.zeros((N3, N2, N1), dtype=np.float32)
-    for cen, axes, rot, rho in ellipsoid_params(n_ell, seed):
+    for cen, axes, rot, rho in (params if params is not None else ellipsoid_params(n_ell, seed)):
         # process one z-slice at a time to bound memory at 512^3
         X1, X2 = np.meshgrid(ax[0], ax[1], indexing="xy")  # [N2, N1]
         for k3 in range(N3):
@@ -174,6 +174,43 @@ def ellipsoid_phantom(dims, n_ell: int = 6, seed: int = 0) -> np.ndarray:
             inside = ((loc / axes) ** 2).sum(-1) <= 1.0
             c[k3][inside] += np.float32(rho)
     return c
+
+
+def ellipsoid_line_integrals(dims, geom, params) -> np.ndarray:
+    """Measured data for a continuous ellipsoid phantom: the exact line
+    integral sum_e rho_e * (chord length of the line through ellipsoid e),
+    for every detector pixel of ``geom`` (float64 [V, R, C]).
+
+    This simulates acquisitions independently of any basis (the role the
+    ASTRA toolbox plays in the paper's experiment).  Ellipsoids are given in
+    the normalised coordinates of ``ellipsoid_params`` (xi = x / ((N-1)/2))."""
+    N = np.asarray(dims, dtype=np.float64)
+    D = 1.0 / np.maximum(0.5 * (N - 1), 0.5)
+    V, R, C = geom.n_views, geom.det_rows, geom.det_cols
+    vec = np.asarray(geom.vecs, dtype=np.float64)
+    ci = np.arange(C) - 0.5 * (C - 1)
+    cj = np.arange(R) - 0.5 * (R - 1)
+    out = np.zeros((V, R, C))
+    for v in range(V):
+        e = vec[v]
+        pix = e[3:6][None, None, :] + ci[None, :, None] * e[6:9] + cj[:, None, None] * e[9:12]
+        if geom.kind == "parallel":
+            d = np.broadcast_to(e[0:3], pix.shape)
+            p = pix
+        else:
+            d = pix - e[0:3]
+            p = np.broadcast_to(e[0:3], pix.shape)
+        d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+        pn, dn = p * D, d * D
+        for cen, axes, rot, rho in params:
+            pp = ((pn - cen) @ rot) / axes
+            dd = (dn @ rot) / axes
+            a = (dd * dd).sum(-1)
+            b = (pp * dd).sum(-1)
+            c0 = (pp * pp).sum(-1) - 1.0
+            disc = b * b - a * c0
+            out[v] += rho * np.where(disc > 0, 2.0 * np.sqrt(np.maximum(disc, 0.0)) / a, 0.0)
+    return out
 
 
 def add_noise(c: np.ndarray, variance: float = 0.01, seed: int = 1) -> np.ndarray:
