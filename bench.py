@@ -58,6 +58,36 @@ def quad_flops_per_pair(n: int, segs_per_pair: float) -> float:
 MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16 + layer 1 + output
 
 
+# HBM bytes per launch of the quadrature kernels on cone_256, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
+# counters read for a plain 256 MiB device copy (x2.000 and x1.000); see
+# profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
+# were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
+QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
+TRAFFIC_SHA256 = "9b2cdf2431957a0235ec12f49b09f35b1a76c4f842c38e2b8f6ce86c8ef6ea32"
+TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
+    ("project_kernel", 3): (2.0 * 46525000 * 1024, 1.0 * 279328 * 1024),
+    ("backproject_kernel", 3): (2.0 * 5600640 * 1024, 1.0 * 72392 * 1024),
+    ("project_kernel", 0): (2.0 * 44882600 * 1024, 1.0 * 258166 * 1024),
+    ("backproject_kernel", 0): (2.0 * 3031270 * 1024, 1.0 * 69136 * 1024),
+}
+
+
+def measured_traffic(kernel: str, degree: int, workload: str):
+    import hashlib
+
+    if workload != "cone_256" or (kernel, degree) not in TRAFFIC_BYTES:
+        return None
+    h = hashlib.sha256()
+    for f in QUAD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_11078_amd", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC_SHA256:
+        return None
+    rd, wr = TRAFFIC_BYTES[(kernel, degree)]
+    return rd + wr
+
+
 def cell_flops(n: int) -> float:
     """Algorithmic FP32 work of one knot cell of the forward walk: at each of
     the m Gauss-Legendre nodes, the n+1 blending weights of three axes
@@ -212,20 +242,23 @@ def main():
                                         f"{quad_flops_per_pair(n, segs_per_pair):.0f} flop per pair x "
                                         f"{pairs_per_ray:.0f} pairs/line")):
                 ach = fl / (ms / 1e3) / 1e12
+                kname = name.split("<")[0]
                 kernels.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
                                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                                "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit})
+                                "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit,
+                                "traffic": measured_traffic(kname, n, wl.name)})
         else:
             fl = total_pairs * MLP_FLOPS_PER_PAIR
             for name, ms in ((f"project_mlp_kernel<{n}>", r0["fwd_ms"]), (f"backproject_mlp_kernel<{n}>", r0["adj_ms"])):
                 ach = fl / (ms / 1e3) / 1e12
                 kernels.append({"kernel": name, "ms": ms, "bound": "mfma", "achieved": ach,
-                                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s", "traffic": None,
                                 "frac": ach / PEAK_BF16_MFMA_TFLOPS,
                                 "work": f"{MLP_FLOPS_PER_PAIR:.0f} matrix-core flop per pair x {pairs_per_ray:.0f} pairs/line"})
         dom = max(kernels, key=lambda k: k["ms"])
         out["roofline"] = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
-                           "unit": dom["unit"], "frac": dom["frac"], "traffic": None, "kernel": dom["kernel"],
+                           "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
+                           "kernel": dom["kernel"],
                            "kernel_ms": dom["ms"], "work": dom["work"]}
         out["kernels"] = kernels
         out["work_counts"] = {"sample_lines": int(cnt_rays.size), "pairs_per_line": pairs_per_ray,
