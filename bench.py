@@ -66,10 +66,10 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
 TRAFFIC_SHA256 = "9b2cdf2431957a0235ec12f49b09f35b1a76c4f842c38e2b8f6ce86c8ef6ea32"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("project_kernel", 3): (2.0 * 46525000 * 1024, 1.0 * 279328 * 1024),
-    ("backproject_kernel", 3): (2.0 * 5600640 * 1024, 1.0 * 72392 * 1024),
-    ("project_kernel", 0): (2.0 * 44882600 * 1024, 1.0 * 258166 * 1024),
-    ("backproject_kernel", 0): (2.0 * 3031270 * 1024, 1.0 * 69136 * 1024),
+    ("project_kernel", 3): (2.0 * 46321785 * 1024, 1.0 * 279275 * 1024),
+    ("backproject_kernel", 3): (2.0 * 5601428 * 1024, 1.0 * 72813 * 1024),
+    ("project_kernel", 0): (2.0 * 44509824 * 1024, 1.0 * 258743 * 1024),
+    ("backproject_kernel", 0): (2.0 * 3004264 * 1024, 1.0 * 69063 * 1024),
 }
 
 

@@ -21,7 +21,7 @@ from gpu_helpers import rel_l2, say, to_gpu, to_np
 pytestmark = pytest.mark.gpu
 
 TOL_QUAD = 1e-5
-TOL_MLP = 1e-2
+TOL_MLP = 1e-3
 _VOLUMES = {}
 
 
@@ -84,14 +84,14 @@ def test_cone_256_quad():
 def test_parallel_128_mlp():
     say("parallel_128 mlp")
     ef, eb = _check("parallel_128", "mlp", n_coefs=1024)
-    assert ef <= TOL_MLP and eb <= 3 * TOL_MLP
+    assert ef <= TOL_MLP and eb <= 2 * TOL_MLP
 
 
 @pytest.mark.skipif(not os.path.exists(default_weights(3)), reason="no trained network weights")
 def test_cone_512_one_batch_mlp():
     say("cone_512, views 0..31, mlp")
     ef, eb = _check("cone_512", "mlp", n_rays=4096, n_coefs=256, views=(0, 32))
-    assert ef <= TOL_MLP and eb <= 3 * TOL_MLP
+    assert ef <= TOL_MLP and eb <= 2 * TOL_MLP
 
 
 def test_cone_512_one_batch_quad():

@@ -149,4 +149,6 @@ def test_network_vs_oracle_small_parallel_32(mctx, blob):
     eb = rel_l2(gb, wb)
     say(f"  forward rel-L2 {e:.3e}, adjoint rel-L2 {eb:.3e} (blob fit fp32 {blob['rel_fp32']:.2e}, "
         f"bf16 {blob['rel_bf16']:.2e})")
-    assert e <= 1e-2 and eb <= 5e-2
+    # trained degree-3 weights: footprint fit 2.3e-3 (BF16); line sums average
+    # the per-pair errors, a noise sinogram back-projected does not
+    assert e <= 1e-3 and eb <= 5e-3
