@@ -29,6 +29,8 @@ struct ss_ctx {
     std::vector<float> last_vecs;   // host copy of what d_geom holds
     double *d_partials = nullptr;   // dot-product partial sums
     void *d_mlp = nullptr;          // network weights in kernel layout
+    float *d_cells = nullptr;       // knot-cell table of the quadrature adjoint
+    int64_t cells_cap = 0;          // floats
 };
 
 namespace ss {
@@ -169,6 +171,25 @@ ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
     return SS_OK;
 }
 
+// Make the knot-cell table hold at least `need` floats.
+ss_status ensure_cells(ss_ctx *ctx, int64_t need) {
+    if (need <= ctx->cells_cap) return SS_OK;
+    hipError_t e;
+    if (ctx->d_cells) {
+        // the old table may still be in use by enqueued work: wait for it
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->d_cells);
+        ctx->d_cells = nullptr;
+        ctx->cells_cap = 0;
+    }
+    if ((e = hipMalloc(&ctx->d_cells, (size_t)need * sizeof(float))) != hipSuccess) {
+        ctx->d_cells = nullptr;
+        return fail(SS_ENOMEM, "knot-cell table (%lld bytes): %s", (long long)need * 4, hipGetErrorString(e));
+    }
+    ctx->cells_cap = need;
+    return SS_OK;
+}
+
 ss_status check_ctx(const ss_ctx *ctx) {
     if (!ctx) return fail(SS_EINVAL, "context is NULL");
     return SS_OK;
@@ -251,6 +272,7 @@ ss_status ss_destroy(ss_ctx *ctx) {
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     if (ctx->d_mlp) (void)hipFree(ctx->d_mlp);
+    if (ctx->d_cells) (void)hipFree(ctx->d_cells);
     delete ctx;
     return SS_OK;
 }
@@ -285,6 +307,11 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
     } else {
         a.sino_in = in;
         a.coeffs_out = out;
+        if (ctx->form == SS_FORM_QUAD_FP32) {
+            if (ss_status s = ensure_cells(ctx, ss::backproject_quad_scratch_floats(ctx->degree, a.N))) return s;
+            a.scratch = ctx->d_cells;
+            a.scratch_floats = ctx->cells_cap;
+        }
         e = ctx->form == SS_FORM_QUAD_FP32 ? ss::launch_backproject_quad(ctx->degree, a, st)
                                            : ss::launch_backproject_mlp(ctx->degree, a, st);
     }

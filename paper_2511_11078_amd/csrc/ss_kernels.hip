@@ -1,75 +1,17 @@
 // ss_kernels.hip -- gfx950 kernels of the spline x-ray transform.
 //
 //   project_kernel      forward model, one line per lane (quadrature form)
-//   backproject_kernel  transpose, one coefficient per lane, atomic-free
+//   backproject_cells_kernel + cells_to_coeffs_kernel
+//                       transpose: knot-cell gather, then coefficient gather (atomic-free)
 //   footprint_kernel    P phi(w, x) for arbitrary pairs (diagnostics)
 //   dot / axpy / xpay / ratio kernels for the least-squares loop
 //
 // The network form lives in ss_mlp.hip and reuses the traversal below.
 #include "ss_kernels.hpp"
 
-namespace ss {
+#include <algorithm>
 
-// ---------------------------------------------------------------------------
-// Forward: the slab walk of one line.  For every slab j of the dominant axis
-// (one DDA step of the paper's projection algorithm), the candidate bases
-// are those with q_d = j and |q_i - P_i(j)| < h (1 + |r_i|) in the two
-// transverse axes, where P(j) is where the line crosses the plane of slab j
-// (the neighbour set of the crossed cells, restricted to bases the line can
-// reach; see the derivation of the window in the module header of
-// ss_kernels.hpp).  Each candidate is gated by the exact chord test inside
-// the footprint and visited exactly once.
-// ---------------------------------------------------------------------------
-template <int n, class Visit>
-__device__ __forceinline__ void walk_line(const LineD &L, const int N[3], Visit &&visit) {
-    constexpr double h = (double)Degree<n>::h;
-    int d, i1, i2;
-    dominant_axis(L.w, d, i1, i2);
-    const double wd = pick3(L.w, d);
-    const double r1 = pick3(L.w, i1) / wd, r2 = pick3(L.w, i2) / wd;
-    const double o[3] = {-0.5 * (N[0] - 1), -0.5 * (N[1] - 1), -0.5 * (N[2] - 1)};
-    // crossing point of slab j in index coordinates: P_i(j) = A_i + j r_i
-    const double ad = pick3(L.a, d) - pick3(o, d);
-    const double A1 = (pick3(L.a, i1) - pick3(o, i1)) - ad * r1;
-    const double A2 = (pick3(L.a, i2) - pick3(o, i2)) - ad * r2;
-    const double H1 = h * (1.0 + fabs(r1)), H2 = h * (1.0 + fabs(r2));
-    const int Nd = pick3(N, d), N1 = pick3(N, i1), N2 = pick3(N, i2);
-    // slabs where both windows can be non-empty: -H < P_i(j) < N_i - 1 + H
-    double jlo = 0.0, jhi = (double)(Nd - 1);
-    {
-        const double rr[2] = {r1, r2}, AA[2] = {A1, A2}, HH[2] = {H1, H2};
-        const int NN[2] = {N1, N2};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const double lo = -HH[k] - AA[k], hi = (double)(NN[k] - 1) + HH[k] - AA[k];
-            if (rr[k] == 0.0) {
-                if (!(lo < 0.0 && hi > 0.0)) jhi = -1.0;
-            } else {
-                const double ta = lo / rr[k], tb = hi / rr[k];
-                jlo = fmax(jlo, floor(fmin(ta, tb)));
-                jhi = fmin(jhi, ceil(fmax(ta, tb)));
-            }
-        }
-    }
-    const Slopes S = make_slopes((float)r1, (float)r2);
-    // clamp in FP64 before converting: every index below stays in [0, N - 1]
-    const int j0 = (int)fmin(fmax(jlo, 0.0), (double)Nd);
-    const int j1 = (int)fmax(fmin(jhi, (double)(Nd - 1)), -1.0);
-    for (int j = j0; j <= j1; ++j) {
-        const double P1 = fma((double)j, r1, A1), P2 = fma((double)j, r2, A2);
-        const int lo1 = (int)fmin(fmax(floor(P1 - H1) + 1.0, 0.0), (double)N1);
-        const int hi1 = (int)fmax(fmin(ceil(P1 + H1) - 1.0, (double)(N1 - 1)), -1.0);
-        const int lo2 = (int)fmin(fmax(floor(P2 - H2) + 1.0, 0.0), (double)N2);
-        const int hi2 = (int)fmax(fmin(ceil(P2 + H2) - 1.0, (double)(N2 - 1)), -1.0);
-        for (int q2 = lo2; q2 <= hi2; ++q2) {
-            const float u2 = (float)(P2 - (double)q2);
-            for (int q1 = lo1; q1 <= hi1; ++q1) {
-                const float u1 = (float)(P1 - (double)q1);
-                visit(S, u1, u2, d, j, i1, q1, i2, q2);
-            }
-        }
-    }
-}
+namespace ss {
 
 // ---------------------------------------------------------------------------
 // Forward, quadrature form: cell walk.  The footprint of a basis is the sum,
@@ -227,140 +169,283 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: brick gather.  A block owns a BX x BY x BZ brick of coefficients,
-// one per thread, and loops over the views.  Per view it maps the brick's
-// support box to a pixel rectangle, sets those lines up once (FP64, anchor
-// re-based near the brick centre) into an LDS table, then every thread sums
-// y_m * footprint over the pixels of its own support's rectangle.  Each
-// coefficient is written once, by its owner: no atomics, deterministic.
+// Adjoint, quadrature form: cell gather, two passes, no atomics.
+//
+// The transpose of the forward cell walk: line m adds y_m times the
+// Gauss-Legendre integral, over its chord through knot cell K, of the
+// restriction of basis q to the line, for each of the (n+1)^3 bases q whose
+// support covers K.  Pass 1 gives every knot cell to one thread, which
+// gathers, over all views, the lines of the pixels whose centres fall in the
+// detector shadow of its cell and accumulates the (n+1)^3 per-basis
+// integrals (T[K][a] below, a = q - K - qoff per axis).  Pass 2 gives every
+// coefficient to one thread, which adds its (n+1)^3 entries T[q - qoff - a][a]
+// of the cells its support covers.  Every (line, basis) pair of eq. (4)
+// is evaluated through the same per-cell Gauss-Legendre terms as the
+// forward, each output has a single writer, and the summation order is
+// fixed.
+//
+// Pass 1 blocks own GX x GY x GZ bricks of cells.  Per view a block projects
+// the brick's lattice corners once (FP64) into LDS, sets the lines of the
+// brick's pixel rectangle up once (FP64, anchor re-based at the brick centre)
+// into an LDS table, and every thread takes the bounding rectangle of its
+// own cell's eight projected corners as its candidate pixels: first it marks
+// the candidates whose chord through the cell is non-empty, then it
+// integrates only those, so the wave runs as many integration rounds as its
+// busiest lane has hits rather than as it has candidates.
+//
+// The cell table T holds (n+1)^3 FP32 entries per cell, entry-major
+// (T[a * cells + K], K x-fastest over the cells of a z-chunk), so that both
+// passes access it coalesced.  Volumes whose table would exceed the
+// context's scratch are processed in overlapping z-chunks of cell layers:
+// a chunk of L layers finalises L - n coefficient layers.
 // ---------------------------------------------------------------------------
-constexpr int BX = 8, BY = 8, BZ = 4;
-constexpr int RAY_CAP = 1024;  // lines per LDS chunk
+constexpr int GX = 8, GY = 8, GZ = 4;
+constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
+constexpr int CRAY_CAP = 512;                   // lines per LDS chunk
+constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
-struct RayRec {      // 48 bytes
+struct CellRay {     // 48 bytes
     float a[3];      // point of the line nearest the brick centre, relative to it
-    float r1, r2, ir1, ir2;
-    float len;       // 1 / |w_d|
-    float y;
-    int d;
-    int pad0, pad1;
+    float w[3];      // unit direction
+    float iw[3];     // 1 / w_k, 0 where w_k == 0
+    float y;         // sinogram value
+    int zmask;       // bit k set: w_k == 0
+    int pad;
 };
 
-template <int n>
-__device__ __forceinline__ void fill_ray(RayRec &rec, const float *__restrict__ e, int kind, int R, int C, int j,
-                                         int i, const double centre[3], float yval) {
+__device__ __forceinline__ void fill_cellray(CellRay &rec, const float *__restrict__ e, int kind, int R, int C, int j,
+                                             int i, const double centre[3], float yval) {
     const LineD L = make_line(e, kind, R, C, j, i, centre);
-    int d, i1, i2;
-    dominant_axis(L.w, d, i1, i2);
-    const double wd = pick3(L.w, d);
-    const double r1 = pick3(L.w, i1) / wd, r2 = pick3(L.w, i2) / wd;
-    const Slopes S = make_slopes((float)r1, (float)r2);
-    // re-based anchor (nearest point to the brick centre), relative to it
-    rec.a[0] = (float)(L.a[0] - centre[0]);
-    rec.a[1] = (float)(L.a[1] - centre[1]);
-    rec.a[2] = (float)(L.a[2] - centre[2]);
-    rec.r1 = S.r1; rec.r2 = S.r2; rec.ir1 = S.ir1; rec.ir2 = S.ir2;
-    rec.len = (float)(1.0 / fabs(wd));
+    int zm = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // a degenerate line is put far outside every cell
+        rec.a[k] = L.ok ? (float)(L.a[k] - centre[k]) : 1.0e30f;
+        rec.w[k] = (float)L.w[k];
+        rec.iw[k] = rec.w[k] != 0.0f ? (float)(1.0 / L.w[k]) : 0.0f;
+        zm |= rec.w[k] == 0.0f ? (1 << k) : 0;
+    }
     rec.y = L.ok ? yval : 0.0f;
-    rec.d = d;
+    rec.zmask = L.ok ? zm : 7;
+    rec.pad = 0;
+}
+
+// Chord [t0, t1] of a line through the cell [lo, lo + 1]^3 (coordinates
+// relative to the brick centre).  A line parallel to a knot plane belongs to
+// the cell above it when it lies in the plane (the forward walk's choice);
+// for degree 0 the support is open and such a line meets neither cell.
+template <int n>
+__device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], float &t0, float &t1) {
+    bool in = true;
+    t0 = -3.0e38f;
+    t1 = 3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (r.zmask & (1 << k)) {
+            in = in && (n == 0 ? lo[k] < r.a[k] : lo[k] <= r.a[k]) && r.a[k] < lo[k] + 1.0f;
+        } else {
+            const float ta = (lo[k] - r.a[k]) * r.iw[k], tb = (lo[k] + 1.0f - r.a[k]) * r.iw[k];
+            t0 = fmaxf(t0, fminf(ta, tb));
+            t1 = fminf(t1, fmaxf(ta, tb));
+        }
+    }
+    return in && t0 < t1;
 }
 
 template <int n>
-__global__ void __launch_bounds__(256) backproject_kernel(const float *__restrict__ y, int N0, int N1, int N2,
-                                                          const float *__restrict__ geom, int kind, int V, int R,
-                                                          int C, float *__restrict__ c) {
-    __shared__ RayRec rays[RAY_CAP];
+__global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2,
+                                                                const float *__restrict__ geom, int kind, int V,
+                                                                int R, int C, int mz0, int L,
+                                                                float *__restrict__ T) {
+    using Rule = GLRule<Degree<n>::m>;
+    constexpr int NB = n + 1;
+    constexpr int qoff = CellBasis<n>::qoff;
+    constexpr double kap = (double)Degree<n>::kap;
+    __shared__ CellRay rays[CRAY_CAP];
+    __shared__ float2 corner[NCORNER];
     __shared__ ViewProj vp;
     __shared__ int sbox[4];
-    const int nbx = (N0 + BX - 1) / BX, nby = (N1 + BY - 1) / BY, nbz = (N2 + BZ - 1) / BZ;
+    const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
+    const int nbx = (M0 + GX - 1) / GX, nby = (M1 + GY - 1) / GY, nbz = (L + GZ - 1) / GZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int tid = threadIdx.x;
-    const int k0 = bx * BX + (tid % BX), k1 = by * BY + ((tid / BX) % BY), k2 = bz * BZ + tid / (BX * BY);
-    const bool mine = k0 < N0 && k1 < N1 && k2 < N2;
-    constexpr double h = (double)Degree<n>::h;
-    const double o[3] = {-0.5 * (N0 - 1), -0.5 * (N1 - 1), -0.5 * (N2 - 1)};
-    // brick centre (world) and this coefficient's position relative to it
-    const double centre[3] = {o[0] + bx * BX + 0.5 * (BX - 1), o[1] + by * BY + 0.5 * (BY - 1),
-                              o[2] + bz * BZ + 0.5 * (BZ - 1)};
-    const float xq[3] = {(float)(o[0] + k0 - centre[0]), (float)(o[1] + k1 - centre[1]),
-                         (float)(o[2] + k2 - centre[2])};
-    // FP32 sums within a view, accumulated across views in FP64
-    double acc = 0.0;
+    const int tx = tid % GX, ty = (tid / GX) % GY, tz = tid / (GX * GY);
+    const int c0 = bx * GX + tx, c1 = by * GY + ty, c2 = bz * GZ + tz;  // cell, chunk-relative
+    const bool mine = c0 < M0 && c1 < M1 && c2 < L;
+    // first cell of the brick in index units (cell K spans [K + kap, K + kap + 1]
+    // in coordinates x + (N - 1)/2), and the brick centre in world coordinates
+    const int mlo = -qoff - n;
+    const double centre[3] = {(double)(mlo + bx * GX) + kap - 0.5 * (N0 - 1) + 0.5 * GX,
+                              (double)(mlo + by * GY) + kap - 0.5 * (N1 - 1) + 0.5 * GY,
+                              (double)(mz0 + bz * GZ) + kap - 0.5 * (N2 - 1) + 0.5 * GZ};
+    // this cell's low corner relative to the brick centre (exact)
+    const float lo[3] = {(float)tx - 0.5f * GX, (float)ty - 0.5f * GY, (float)tz - 0.5f * GZ};
+    const float oc = 0.5f * (float)(C - 1), orow = 0.5f * (float)(R - 1);
+    float acc[NB * NB * NB];
+#pragma unroll
+    for (int e = 0; e < NB * NB * NB; ++e) acc[e] = 0.0f;
+
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
-        float part = 0.0f;
         if (tid == 0) {
             make_viewproj(e, kind, vp);
-            double lo[3], hi[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int nb = k == 0 ? BX : k == 1 ? BY : BZ;
-                lo[k] = centre[k] - 0.5 * (nb - 1) - h;
-                hi[k] = centre[k] + 0.5 * (nb - 1) + h;
-            }
-            box_to_pixels(vp, lo, hi, R, C, sbox[0], sbox[1], sbox[2], sbox[3]);
+            double blo[3], bhi[3];
+            blo[0] = centre[0] - 0.5 * GX; bhi[0] = centre[0] + 0.5 * GX;
+            blo[1] = centre[1] - 0.5 * GY; bhi[1] = centre[1] + 0.5 * GY;
+            blo[2] = centre[2] - 0.5 * GZ; bhi[2] = centre[2] + 0.5 * GZ;
+            box_to_pixels(vp, blo, bhi, R, C, sbox[0], sbox[1], sbox[2], sbox[3]);
         }
         __syncthreads();
+        // detector position (pixel units) of every lattice corner of the brick
+        for (int t = tid; t < NCORNER; t += blockDim.x) {
+            const int cx = t % (GX + 1), cy = (t / (GX + 1)) % (GY + 1), cz = t / ((GX + 1) * (GY + 1));
+            const double X[3] = {centre[0] + (double)cx - 0.5 * GX, centre[1] + (double)cy - 0.5 * GY,
+                                 centre[2] + (double)cz - 0.5 * GZ};
+            double cc, rr;
+            corner[t] = to_detector(vp, X, cc, rr) ? make_float2((float)cc + oc, (float)rr + orow)
+                                                   : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        }
         const int bi0 = sbox[0], bi1 = sbox[1], bj0 = sbox[2], bj1 = sbox[3];
-        // this coefficient's own rectangle
+        __syncthreads();
+        // this cell's candidate pixels: the bounding rectangle of its corners
         int mi0 = 0, mi1 = -1, mj0 = 0, mj1 = -1;
         if (mine) {
-            double lo[3], hi[3];
+            float cmin = 3.0e38f, cmax = -3.0e38f, rmin = 3.0e38f, rmax = -3.0e38f;
+            bool bad = false;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = centre[k] + (double)xq[k] - h;
-                hi[k] = centre[k] + (double)xq[k] + h;
+            for (int k = 0; k < 8; ++k) {
+                const float2 p = corner[((tz + (k >> 2)) * (GY + 1) + ty + ((k >> 1) & 1)) * (GX + 1) + tx + (k & 1)];
+                bad = bad || p.x != p.x;
+                cmin = fminf(cmin, p.x); cmax = fmaxf(cmax, p.x);
+                rmin = fminf(rmin, p.y); rmax = fmaxf(rmax, p.y);
             }
-            box_to_pixels(vp, lo, hi, R, C, mi0, mi1, mj0, mj1);
+            if (bad) {
+                mi0 = 0; mi1 = C - 1; mj0 = 0; mj1 = R - 1;
+            } else {
+                // clamped in FP32 before converting
+                const float fi0 = fmaxf(ceilf(cmin - PIX_MARGIN), 0.0f);
+                const float fi1 = fminf(floorf(cmax + PIX_MARGIN), (float)(C - 1));
+                const float fj0 = fmaxf(ceilf(rmin - PIX_MARGIN), 0.0f);
+                const float fj1 = fminf(floorf(rmax + PIX_MARGIN), (float)(R - 1));
+                if (fi0 <= fi1 && fj0 <= fj1) {
+                    mi0 = (int)fi0; mi1 = (int)fi1; mj0 = (int)fj0; mj1 = (int)fj1;
+                }
+            }
         }
         const int W = bi1 - bi0 + 1;
-        const int rows_per_chunk = W > 0 ? max(1, RAY_CAP / W) : 1;
+        const int rows_per_chunk = W > 0 ? max(1, CRAY_CAP / W) : 1;
         for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_chunk) {
             const int cj1 = min(bj1, cj0 + rows_per_chunk - 1);
-            const int cnt = (cj1 - cj0 + 1) * W;
-            // W can exceed RAY_CAP only for absurd geometries; then split columns
-            const int cols = min(W, RAY_CAP);
+            const int cols = min(W, CRAY_CAP);
             for (int ci0 = bi0; ci0 <= bi1; ci0 += cols) {
                 const int ci1 = min(bi1, ci0 + cols - 1);
                 const int cw = ci1 - ci0 + 1;
-                const int cn = min(cnt, (cj1 - cj0 + 1) * cw);
+                const int cn = (cj1 - cj0 + 1) * cw;
                 __syncthreads();
                 for (int t = tid; t < cn; t += blockDim.x) {
                     const int jj = cj0 + t / cw, ii = ci0 + t % cw;
-                    fill_ray<n>(rays[t], e, kind, R, C, jj, ii, centre, y[((int64_t)v * R + jj) * C + ii]);
+                    fill_cellray(rays[t], e, kind, R, C, jj, ii, centre, y[((int64_t)v * R + jj) * C + ii]);
                 }
                 __syncthreads();
-                if (mine) {
-                    const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
-                    const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
-                    for (int jj = j0; jj <= j1; ++jj) {
-                        for (int ii = i0; ii <= i1; ++ii) {
-                            const RayRec &rr = rays[(jj - cj0) * cw + (ii - ci0)];
-                            const int d = rr.d;
-                            const int i1x = d == 0 ? 1 : 0, i2x = d == 2 ? 1 : 2;
-                            const float ad = d == 0 ? rr.a[0] : d == 1 ? rr.a[1] : rr.a[2];
-                            const float xd = d == 0 ? xq[0] : d == 1 ? xq[1] : xq[2];
-                            const float a1 = i1x == 0 ? rr.a[0] : rr.a[1];
-                            const float x1 = i1x == 0 ? xq[0] : xq[1];
-                            const float a2 = i2x == 1 ? rr.a[1] : rr.a[2];
-                            const float x2 = i2x == 1 ? xq[1] : xq[2];
-                            const float t = xd - ad;
-                            const float u1 = fmaf(t, rr.r1, a1) - x1;
-                            const float u2 = fmaf(t, rr.r2, a2) - x2;
-                            Slopes S;
-                            S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
-                            const float f = footprint_slab<n>(S, u1, u2);
-                            if (f != 0.0f) part = fmaf(rr.y * rr.len, f, part);
+                const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
+                const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
+                const int nw = i1 - i0 + 1;
+                const int ncand = (nw > 0 && j1 >= j0) ? nw * (j1 - j0 + 1) : 0;
+                for (int base = 0; base < ncand; base += 32) {
+                    // mark the candidates whose chord through the cell is non-empty
+                    uint32_t hits = 0;
+                    const int cnt = min(32, ncand - base);
+                    int jr = base / nw, ir = base - jr * nw;
+                    for (int k = 0; k < cnt; ++k) {
+                        const CellRay &r = rays[(j0 + jr - cj0) * cw + (i0 + ir - ci0)];
+                        float t0, t1;
+                        if (cell_chord<n>(r, lo, t0, t1)) hits |= 1u << k;
+                        if (++ir == nw) { ir = 0; ++jr; }
+                    }
+                    // integrate those
+                    while (hits) {
+                        const int k = __builtin_ctz(hits);
+                        hits &= hits - 1u;
+                        const int idx = base + k;
+                        const int jr = idx / nw;
+                        const CellRay &r = rays[(j0 + jr - cj0) * cw + (i0 + idx - jr * nw - ci0)];
+                        float t0, t1;
+                        cell_chord<n>(r, lo, t0, t1);
+                        const float mid = 0.5f * (t0 + t1), half = 0.5f * (t1 - t0);
+                        float lc[3], dl[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            lc[q] = fmaf(mid, r.w[q], r.a[q]) - lo[q];
+                            dl[q] = half * r.w[q];
+                        }
+                        const float sc = half * r.y;
+#pragma unroll
+                        for (int l = 0; l < Rule::m; ++l) {
+                            const float xi = Rule::x(l);
+                            float w1[NB], w2[NB], w3[NB];
+                            cell_weights<n>(fmaf(dl[0], xi, lc[0]), w1);
+                            cell_weights<n>(fmaf(dl[1], xi, lc[1]), w2);
+                            cell_weights<n>(fmaf(dl[2], xi, lc[2]), w3);
+                            const float g = Rule::w(l) * sc;
+#pragma unroll
+                            for (int a1 = 0; a1 < NB; ++a1) w1[a1] *= g;
+#pragma unroll
+                            for (int a3 = 0; a3 < NB; ++a3)
+#pragma unroll
+                                for (int a2 = 0; a2 < NB; ++a2) {
+                                    const float p = w3[a3] * w2[a2];
+#pragma unroll
+                                    for (int a1 = 0; a1 < NB; ++a1)
+                                        acc[(a3 * NB + a2) * NB + a1] = fmaf(p, w1[a1], acc[(a3 * NB + a2) * NB + a1]);
+                                }
                         }
                     }
                 }
             }
         }
-        __syncthreads();
-        acc += (double)part;
     }
-    if (mine) c[((int64_t)k2 * N1 + k1) * N0 + k0] = (float)acc;
+    if (mine) {
+        const int64_t cells = (int64_t)M0 * M1 * L;
+        const int64_t K = ((int64_t)c2 * M1 + c1) * M0 + c0;
+#pragma unroll
+        for (int a = 0; a < NB * NB * NB; ++a) T[a * cells + K] = acc[a];
+    }
+}
+
+// Pass 2: coefficient q (layer q2 in [qz0, qz1]) adds T[K][a] over the cells
+// K = q - qoff - a of its support (FP64 sum of the (n+1)^3 FP32 entries).
+template <int n>
+__global__ void __launch_bounds__(256) cells_to_coeffs_kernel(const float *__restrict__ T, int N0, int N1,
+                                                              int mz0, int L, int qz0, int qz1,
+                                                              float *__restrict__ c) {
+    constexpr int NB = n + 1;
+    constexpr int qoff = CellBasis<n>::qoff;
+    const int64_t per = (int64_t)N0 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per * (qz1 - qz0 + 1)) return;
+    const int k2 = qz0 + (int)(idx / per);
+    const int rem = (int)(idx % per);
+    const int k1 = rem / N0, k0 = rem % N0;
+    const int M0 = N0 + n, M1 = N1 + n;
+    const int mlo = -qoff - n;
+    const int64_t cells = (int64_t)M0 * M1 * L;
+    double s = 0.0;
+#pragma unroll
+    for (int a3 = 0; a3 < NB; ++a3) {
+        const int z = k2 - qoff - a3 - mz0;  // in [0, L) for qz0 <= k2 <= qz1
+#pragma unroll
+        for (int a2 = 0; a2 < NB; ++a2) {
+            const int yy = k1 - qoff - a2 - mlo;
+#pragma unroll
+            for (int a1 = 0; a1 < NB; ++a1) {
+                const int xx = k0 - qoff - a1 - mlo;
+                const int64_t K = ((int64_t)z * M1 + yy) * M0 + xx;
+                s += (double)T[((a3 * NB + a2) * NB + a1) * cells + K];
+            }
+        }
+    }
+    c[(int64_t)k2 * per + rem] = (float)s;
 }
 
 // ---------------------------------------------------------------------------
@@ -459,11 +544,40 @@ static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+int64_t backproject_quad_scratch_floats(int degree, const int N[3]) {
+    const int64_t nb = degree + 1;
+    const int64_t layer = nb * nb * nb * (int64_t)(N[0] + degree) * (N[1] + degree);
+    const int64_t full = layer * (N[2] + degree);
+    // at least 4 (n + 1) layers per chunk, so that chunking re-does at most
+    // a quarter of the cell layers
+    const int64_t floor_layers = std::min<int64_t>(N[2] + degree, 4 * nb);
+    return std::min(full, std::max(CELL_SCRATCH_FLOATS, layer * floor_layers));
+}
+
 template <int n>
 static hipError_t launch_backproject_n(const LaunchArgs &a, hipStream_t st) {
-    const int nb = ((a.N[0] + BX - 1) / BX) * ((a.N[1] + BY - 1) / BY) * ((a.N[2] + BZ - 1) / BZ);
-    hipLaunchKernelGGL(backproject_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1], a.N[2],
-                       a.geom, a.kind, a.V, a.R, a.C, a.coeffs_out);
+    constexpr int qoff = CellBasis<n>::qoff;
+    constexpr int64_t NB3 = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    const int M0 = a.N[0] + n, M1 = a.N[1] + n, M2 = a.N[2] + n;
+    const int64_t layer = NB3 * M0 * M1;
+    const int Lmax = (int)std::min<int64_t>(M2, a.scratch_floats / layer);
+    if (!a.scratch || Lmax <= n) return hipErrorInvalidValue;
+    const int mlo = -qoff - n;
+    const int64_t plane = (int64_t)a.N[0] * a.N[1];
+    for (int s = mlo;;) {
+        const int L = std::min(Lmax, mlo + M2 - s);
+        const int nb = ((M0 + GX - 1) / GX) * ((M1 + GY - 1) / GY) * ((L + GZ - 1) / GZ);
+        hipLaunchKernelGGL(backproject_cells_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1],
+                           a.N[2], a.geom, a.kind, a.V, a.R, a.C, s, L, a.scratch);
+        const int qz0 = s + qoff + n, qz1 = std::min(s + L - 1 + qoff, a.N[2] - 1);
+        if (qz1 >= qz0) {
+            const int64_t cnt = plane * (qz1 - qz0 + 1);
+            hipLaunchKernelGGL(cells_to_coeffs_kernel<n>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                               a.scratch, a.N[0], a.N[1], s, L, qz0, qz1, a.coeffs_out);
+        }
+        if (s + L >= mlo + M2) break;
+        s += L - n;
+    }
     return hipGetLastError();
 }
 

@@ -33,7 +33,15 @@ struct LaunchArgs {
     int N[3];
     int kind, V, R, C;
     const void *mlp;       // device weights (network form)
+    float *scratch;        // quadrature adjoint: knot-cell table
+    int64_t scratch_floats;
 };
+
+// Largest knot-cell table of the quadrature adjoint: 2^31 floats (8 GiB);
+// larger volumes are processed in z-chunks of cell layers.
+constexpr int64_t CELL_SCRATCH_FLOATS = (int64_t)1 << 31;
+// Table size the quadrature adjoint uses for a volume of N[0] x N[1] x N[2].
+int64_t backproject_quad_scratch_floats(int degree, const int N[3]);
 
 hipError_t launch_project_quad(int degree, const LaunchArgs &a, hipStream_t st);
 hipError_t launch_backproject_quad(int degree, const LaunchArgs &a, hipStream_t st);
