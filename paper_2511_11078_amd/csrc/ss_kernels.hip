@@ -252,6 +252,39 @@ __device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], 
     return in && t0 < t1;
 }
 
+// Pixels whose centre lies in the bounding rectangle of the projected
+// corners of the lattice box [x0, x0 + sx] x [y0, y0 + sy] x [z0, z0 + sz]
+// (corner table of the brick, pixel units).  The projection of the box is
+// the convex hull of its corners' projections, so every pixel whose line
+// meets the box is in the rectangle; PIX_MARGIN absorbs FP32 rounding.  If a
+// corner has no projection (on or behind the source plane), the whole
+// detector.
+__device__ __forceinline__ void shadow_rect(const float2 *corner, int sx, int sy, int sz, int x0, int y0, int z0,
+                                            int R, int C, int &i0, int &i1, int &j0, int &j1) {
+    float cmin = 3.0e38f, cmax = -3.0e38f, rmin = 3.0e38f, rmax = -3.0e38f;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int cx = x0 + ((k & 1) ? sx : 0), cy = y0 + ((k & 2) ? sy : 0), cz = z0 + ((k & 4) ? sz : 0);
+        const float2 p = corner[(cz * (GY + 1) + cy) * (GX + 1) + cx];
+        bad = bad || p.x != p.x || p.y != p.y;
+        cmin = fminf(cmin, p.x); cmax = fmaxf(cmax, p.x);
+        rmin = fminf(rmin, p.y); rmax = fmaxf(rmax, p.y);
+    }
+    if (bad) {
+        i0 = 0; i1 = C - 1; j0 = 0; j1 = R - 1;
+        return;
+    }
+    // clamped in FP32 before converting
+    const float fi0 = fmaxf(ceilf(cmin - PIX_MARGIN), 0.0f), fi1 = fminf(floorf(cmax + PIX_MARGIN), (float)(C - 1));
+    const float fj0 = fmaxf(ceilf(rmin - PIX_MARGIN), 0.0f), fj1 = fminf(floorf(rmax + PIX_MARGIN), (float)(R - 1));
+    if (fi0 <= fi1 && fj0 <= fj1) {
+        i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
+    } else {
+        i0 = 0; i1 = -1; j0 = 0; j1 = -1;
+    }
+}
+
 template <int n>
 __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2,
                                                                 const float *__restrict__ geom, int kind, int V,
@@ -264,7 +297,6 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     __shared__ CellRay rays[CRAY_CAP];
     __shared__ float2 corner[NCORNER];
     __shared__ ViewProj vp;
-    __shared__ int sbox[4];
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
     const int nbx = (M0 + GX - 1) / GX, nby = (M1 + GY - 1) / GY, nbz = (L + GZ - 1) / GZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -288,14 +320,7 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
 
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
-        if (tid == 0) {
-            make_viewproj(e, kind, vp);
-            double blo[3], bhi[3];
-            blo[0] = centre[0] - 0.5 * GX; bhi[0] = centre[0] + 0.5 * GX;
-            blo[1] = centre[1] - 0.5 * GY; bhi[1] = centre[1] + 0.5 * GY;
-            blo[2] = centre[2] - 0.5 * GZ; bhi[2] = centre[2] + 0.5 * GZ;
-            box_to_pixels(vp, blo, bhi, R, C, sbox[0], sbox[1], sbox[2], sbox[3]);
-        }
+        if (tid == 0) make_viewproj(e, kind, vp);
         __syncthreads();
         // detector position (pixel units) of every lattice corner of the brick
         for (int t = tid; t < NCORNER; t += blockDim.x) {
@@ -306,33 +331,13 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
             corner[t] = to_detector(vp, X, cc, rr) ? make_float2((float)cc + oc, (float)rr + orow)
                                                    : make_float2(__builtin_nanf(""), __builtin_nanf(""));
         }
-        const int bi0 = sbox[0], bi1 = sbox[1], bj0 = sbox[2], bj1 = sbox[3];
         __syncthreads();
-        // this cell's candidate pixels: the bounding rectangle of its corners
+        // the brick's pixel rectangle (from its eight corners, the same for
+        // every thread) and this cell's candidate pixels (from its own)
+        int bi0, bi1, bj0, bj1;
+        shadow_rect(corner, GX, GY, GZ, 0, 0, 0, R, C, bi0, bi1, bj0, bj1);
         int mi0 = 0, mi1 = -1, mj0 = 0, mj1 = -1;
-        if (mine) {
-            float cmin = 3.0e38f, cmax = -3.0e38f, rmin = 3.0e38f, rmax = -3.0e38f;
-            bool bad = false;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float2 p = corner[((tz + (k >> 2)) * (GY + 1) + ty + ((k >> 1) & 1)) * (GX + 1) + tx + (k & 1)];
-                bad = bad || p.x != p.x;
-                cmin = fminf(cmin, p.x); cmax = fmaxf(cmax, p.x);
-                rmin = fminf(rmin, p.y); rmax = fmaxf(rmax, p.y);
-            }
-            if (bad) {
-                mi0 = 0; mi1 = C - 1; mj0 = 0; mj1 = R - 1;
-            } else {
-                // clamped in FP32 before converting
-                const float fi0 = fmaxf(ceilf(cmin - PIX_MARGIN), 0.0f);
-                const float fi1 = fminf(floorf(cmax + PIX_MARGIN), (float)(C - 1));
-                const float fj0 = fmaxf(ceilf(rmin - PIX_MARGIN), 0.0f);
-                const float fj1 = fminf(floorf(rmax + PIX_MARGIN), (float)(R - 1));
-                if (fi0 <= fi1 && fj0 <= fj1) {
-                    mi0 = (int)fi0; mi1 = (int)fi1; mj0 = (int)fj0; mj1 = (int)fj1;
-                }
-            }
-        }
+        if (mine) shadow_rect(corner, 1, 1, 1, tx, ty, tz, R, C, mi0, mi1, mj0, mj1);
         const int W = bi1 - bi0 + 1;
         const int rows_per_chunk = W > 0 ? max(1, CRAY_CAP / W) : 1;
         for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_chunk) {
