@@ -45,16 +45,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def quad_flops_per_pair(n: int, segs_per_pair: float) -> float:
-    """Algorithmic FP32 work of one exact footprint: on every polynomial
-    segment m Gauss-Legendre nodes, each with 3 Horner evaluations of degree n
-    (n FMA each), 2 products, 1 node map and 1 weighted accumulation
-    (3n + 4 FMA-class operations, 2 flops each), plus ~60 flops of chord and
-    knot set-up per pair."""
-    m = GL_ORDER[n]
-    return segs_per_pair * m * (3 * n + 4) * 2.0 + 60.0
-
-
+N_SAMPLE_LINES = 262144   # parity and CPU-baseline samples (about 10 s of oracle work)
+N_SAMPLE_COEFS = 32768
 MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16 + layer 1 + output
 
 
@@ -66,17 +58,15 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
 TRAFFIC_SHA256 = "9b2cdf2431957a0235ec12f49b09f35b1a76c4f842c38e2b8f6ce86c8ef6ea32"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("project_kernel", 3): (2.0 * 46321785 * 1024, 1.0 * 279275 * 1024),
-    ("backproject_kernel", 3): (2.0 * 5601428 * 1024, 1.0 * 72813 * 1024),
-    ("project_kernel", 0): (2.0 * 44509824 * 1024, 1.0 * 258743 * 1024),
-    ("backproject_kernel", 0): (2.0 * 3004264 * 1024, 1.0 * 69063 * 1024),
 }
 
 
-def measured_traffic(kernel: str, degree: int, workload: str):
+def measured_traffic(kernels, degree: int, workload: str):
+    """HBM bytes of one launch of the named kernels (summed), or None when
+    they were not measured for this workload and these sources."""
     import hashlib
 
-    if workload != "cone_256" or (kernel, degree) not in TRAFFIC_BYTES:
+    if workload != "cone_256" or any((k, degree) not in TRAFFIC_BYTES for k in kernels):
         return None
     h = hashlib.sha256()
     for f in QUAD_SOURCES:
@@ -84,16 +74,17 @@ def measured_traffic(kernel: str, degree: int, workload: str):
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC_SHA256:
         return None
-    rd, wr = TRAFFIC_BYTES[(kernel, degree)]
-    return rd + wr
+    return float(sum(sum(TRAFFIC_BYTES[(k, degree)]) for k in kernels))
 
 
 def cell_flops(n: int) -> float:
-    """Algorithmic FP32 work of one knot cell of the forward walk: at each of
-    the m Gauss-Legendre nodes, the n+1 blending weights of three axes
-    (2n + 3 operations each), the contraction with the (n+1)^3 coefficient
-    block ((n+1)^3 + (n+1)^2 + (n+1) FMA) and 4 operations for the node map
-    and the weighted sum; 2 flops per operation."""
+    """Algorithmic FP32 work of one (line, knot cell) unit: at each of the m
+    Gauss-Legendre nodes, the n+1 blending weights of three axes (2n + 3
+    operations each), the contraction of the (n+1)^3 block with the three
+    weight vectors ((n+1)^3 + (n+1)^2 + (n+1) FMA: the forward contracts the
+    coefficient block, the adjoint accumulates the outer product, the same
+    count) and 4 operations for the node map and the weighted sum; 2 flops
+    per operation."""
     m = GL_ORDER[n]
     nb = n + 1
     return 2.0 * m * (3 * (2 * n + 3) + nb ** 3 + nb ** 2 + nb + 4)
@@ -102,7 +93,7 @@ def cell_flops(n: int) -> float:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["quad", "mlp"], default="quad",
                     help="footprint form of the timed steps")
@@ -179,8 +170,8 @@ def main():
                          "steps": steps, "y": y.cpu().numpy() if fi == 0 else None,
                          "b": b.cpu().numpy().ravel() if fi == 0 else None,
                          "y_sample": None, "b_sample": None}
-        ys = synth.sample_indices(R, 16384, seed=7)
-        cs = synth.sample_indices(int(np.prod(dims)), 4096, seed=8)
+        ys = synth.sample_indices(R, N_SAMPLE_LINES, seed=7)
+        cs = synth.sample_indices(int(np.prod(dims)), N_SAMPLE_COEFS, seed=8)
         results[form]["y_sample"] = y.reshape(-1)[torch.from_numpy(ys).to(dev)].cpu().numpy()
         results[form]["b_sample"] = b.reshape(-1)[torch.from_numpy(cs).to(dev)].cpu().numpy()
         ctx.close()
@@ -201,8 +192,8 @@ def main():
     if not args.no_oracle:
         import oracle
 
-        ys = synth.sample_indices(R, 16384, seed=7)
-        cs = synth.sample_indices(int(np.prod(dims)), 4096, seed=8)
+        ys = synth.sample_indices(R, N_SAMPLE_LINES, seed=7)
+        cs = synth.sample_indices(int(np.prod(dims)), N_SAMPLE_COEFS, seed=8)
         y_adj_in = results[main_form]["y"]
         # oracle on the samples: forward rays, adjoint coefficients (same input y)
         t0 = time.perf_counter()
@@ -210,16 +201,15 @@ def main():
         t_of = time.perf_counter() - t0
         log(f"[bench] oracle forward on {ys.size} lines: {t_of:.1f}s")
         t0 = time.perf_counter()
-        cs_small = cs[:1024]
-        bo = oracle.backproject_subset(y_adj_in, geom, dims, n, coefs=cs_small)
+        bo = oracle.backproject_subset(y_adj_in, geom, dims, n, coefs=cs)
         t_ob = time.perf_counter() - t0
-        log(f"[bench] oracle adjoint on {cs_small.size} coefficients: {t_ob:.1f}s")
+        log(f"[bench] oracle adjoint on {cs.size} coefficients: {t_ob:.1f}s")
         rel = {}
         for form in forms:
             rf = float(np.linalg.norm(results[form]["y_sample"] - yo) / np.linalg.norm(yo))
             entry = {"forward_rel_l2": rf}
             if form == main_form:
-                ra = float(np.linalg.norm(results[form]["b_sample"][:1024] - bo) / np.linalg.norm(bo))
+                ra = float(np.linalg.norm(results[form]["b_sample"] - bo) / np.linalg.norm(bo))
                 entry["adjoint_rel_l2"] = ra
             rel[form] = entry
         out["rel_l2_vs_oracle"] = rel[main_form]
@@ -234,19 +224,22 @@ def main():
         total_pairs = pairs_per_ray * R
         kernels = []
         if main_form == "quad":
+            nb3 = (n + 1) ** 3
             fl_f = R * cells_per_ray * cell_flops(n)
-            fl_a = total_pairs * quad_flops_per_pair(n, segs_per_pair)
+            # adjoint: the same (line, cell) units, then (n+1)^3 adds per coefficient
+            fl_a = R * cells_per_ray * cell_flops(n) + 2.0 * nb3 * float(np.prod(dims))
             for name, ms, fl, unit in ((f"project_kernel<{n}> (knot-cell walk)", r0["fwd_ms"], fl_f,
-                                        f"{cell_flops(n):.0f} flop per cell x {cells_per_ray:.1f} cells/line"),
-                                       (f"backproject_kernel<{n}> (per-pair brick gather)", r0["adj_ms"], fl_a,
-                                        f"{quad_flops_per_pair(n, segs_per_pair):.0f} flop per pair x "
-                                        f"{pairs_per_ray:.0f} pairs/line")):
+                                        f"{cell_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} cells/line"),
+                                       (f"backproject_cells_kernel<{n}> + cells_to_coeffs_kernel<{n}> "
+                                        f"(knot-cell gather)", r0["adj_ms"], fl_a,
+                                        f"{cell_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} "
+                                        f"cells/line + {2 * nb3} flop per coefficient")):
                 ach = fl / (ms / 1e3) / 1e12
-                kname = name.split("<")[0]
+                knames = [part.strip().split("<")[0] for part in name.split(" (")[0].split("+")]
                 kernels.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
                                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                 "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit,
-                                "traffic": measured_traffic(kname, n, wl.name)})
+                                "traffic": measured_traffic(knames, n, wl.name)})
         else:
             fl = total_pairs * MLP_FLOPS_PER_PAIR
             for name, ms in ((f"project_mlp_kernel<{n}>", r0["fwd_ms"]), (f"backproject_mlp_kernel<{n}>", r0["adj_ms"])):
@@ -266,11 +259,11 @@ def main():
                               "pairs_per_application": total_pairs}
         # CPU baseline: the oracle as it stands, extrapolated from its samples
         t_fwd_all = t_of * R / ys.size
-        t_adj_all = t_ob * float(np.prod(dims)) / cs_small.size
+        t_adj_all = t_ob * float(np.prod(dims)) / cs.size
         out["cpu_baseline"] = {"value": R / (t_fwd_all + t_adj_all), "unit": "rays/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"FP64 oracle: direct line integrals of {ys.size} sampled lines "
-                                         f"({t_of:.1f}s) + voxel-driven adjoint of {cs_small.size} sampled "
+                                         f"({t_of:.1f}s) + voxel-driven adjoint of {cs.size} sampled "
                                          f"coefficients over all {geom.n_views} views ({t_ob:.1f}s), "
                                          f"extrapolated to {R} lines and {int(np.prod(dims))} coefficients"}
         if len(forms) > 1:

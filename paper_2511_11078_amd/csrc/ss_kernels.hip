@@ -378,36 +378,88 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
                         float t0, t1;
                         cell_chord<n>(r, lo, t0, t1);
                         const float mid = 0.5f * (t0 + t1), half = 0.5f * (t1 - t0);
-                        float lc[3], dl[3];
+                        float uc[3], du[3];  // centred cell coordinate at mid, and its step
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
-                            lc[q] = fmaf(mid, r.w[q], r.a[q]) - lo[q];
-                            dl[q] = half * r.w[q];
+                            uc[q] = fmaf(mid, r.w[q], r.a[q]) - (lo[q] + 0.5f);
+                            du[q] = half * r.w[q];
                         }
                         const float sc = half * r.y;
 #pragma unroll
                         for (int l = 0; l < Rule::m; ++l) {
                             const float xi = Rule::x(l);
-                            float w1[NB], w2[NB], w3[NB];
-                            cell_weights<n>(fmaf(dl[0], xi, lc[0]), w1);
-                            cell_weights<n>(fmaf(dl[1], xi, lc[1]), w2);
-                            cell_weights<n>(fmaf(dl[2], xi, lc[2]), w3);
-                            const float g = Rule::w(l) * sc;
+                            // powers u^p of the three centred coordinates (p >= 1)
+                            float P1[NB], P2[NB], P3[NB];
+                            P1[0] = Rule::w(l) * sc;  // axis 1 carries the quadrature weight
+                            P2[0] = 1.0f;
+                            P3[0] = 1.0f;
+                            const float u1 = fmaf(du[0], xi, uc[0]), u2 = fmaf(du[1], xi, uc[1]),
+                                        u3 = fmaf(du[2], xi, uc[2]);
 #pragma unroll
-                            for (int a1 = 0; a1 < NB; ++a1) w1[a1] *= g;
+                            for (int p = 1; p <= n; ++p) {
+                                P1[p] = P1[p - 1] * u1;
+                                P2[p] = p == 1 ? u2 : P2[p - 1] * u2;
+                                P3[p] = p == 1 ? u3 : P3[p - 1] * u3;
+                            }
 #pragma unroll
-                            for (int a3 = 0; a3 < NB; ++a3)
+                            for (int p2 = 0; p2 < NB; ++p2) {
+                                float xy[NB];
 #pragma unroll
-                                for (int a2 = 0; a2 < NB; ++a2) {
-                                    const float p = w3[a3] * w2[a2];
+                                for (int p1 = 0; p1 < NB; ++p1) xy[p1] = p2 == 0 ? P1[p1] : P2[p2] * P1[p1];
 #pragma unroll
-                                    for (int a1 = 0; a1 < NB; ++a1)
-                                        acc[(a3 * NB + a2) * NB + a1] = fmaf(p, w1[a1], acc[(a3 * NB + a2) * NB + a1]);
-                                }
+                                for (int p1 = 0; p1 < NB; ++p1) acc[p2 * NB + p1] += xy[p1];
+#pragma unroll
+                                for (int p3 = 1; p3 < NB; ++p3)
+#pragma unroll
+                                    for (int p1 = 0; p1 < NB; ++p1)
+                                        acc[(p3 * NB + p2) * NB + p1] =
+                                            fmaf(P3[p3], xy[p1], acc[(p3 * NB + p2) * NB + p1]);
+                            }
                         }
                     }
                 }
             }
+        }
+    }
+    // moments -> per-basis integrals: apply the blending map along each axis
+    if constexpr (n > 0) {
+#pragma unroll
+        for (int i = 0; i < NB * NB; ++i) {  // axis 1: index (i, p1)
+            float t[NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                t[a] = 0.0f;
+#pragma unroll
+                for (int p = 0; p < NB; ++p) t[a] = fmaf(blend_u<n>(a, p), acc[i * NB + p], t[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < NB; ++a) acc[i * NB + a] = t[a];
+        }
+#pragma unroll
+        for (int i3 = 0; i3 < NB; ++i3)  // axis 2: index (i3, p2, a1)
+#pragma unroll
+            for (int i1 = 0; i1 < NB; ++i1) {
+                float t[NB];
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    t[a] = 0.0f;
+#pragma unroll
+                    for (int p = 0; p < NB; ++p) t[a] = fmaf(blend_u<n>(a, p), acc[(i3 * NB + p) * NB + i1], t[a]);
+                }
+#pragma unroll
+                for (int a = 0; a < NB; ++a) acc[(i3 * NB + a) * NB + i1] = t[a];
+            }
+#pragma unroll
+        for (int i = 0; i < NB * NB; ++i) {  // axis 3: index (p3, i)
+            float t[NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                t[a] = 0.0f;
+#pragma unroll
+                for (int p = 0; p < NB; ++p) t[a] = fmaf(blend_u<n>(a, p), acc[p * NB * NB + i], t[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < NB; ++a) acc[a * NB * NB + i] = t[a];
         }
     }
     if (mine) {

@@ -161,6 +161,30 @@ __device__ __forceinline__ void cell_weights(float t, float wt[n + 1]) {
     }
 }
 
+// The same blending polynomials in the centred coordinate u = t - 1/2
+// (|u| <= 1/2 inside the cell): wt[a] = sum_p blend_u<n>(a, p) u^p.  Sums of
+// products of powers of u (moments) accumulated over many lines convert to
+// sums of products of weights by one linear map per axis; centring keeps
+// that map well conditioned (the powers are at most 2^-p).
+template <int n>
+__host__ __device__ constexpr float blend_u(int a, int p) {
+    if constexpr (n == 0) {
+        return 1.0f;
+    } else if constexpr (n == 1) {
+        constexpr float B[2][2] = {{0.5f, -1.0f}, {0.5f, 1.0f}};
+        return B[a][p];
+    } else if constexpr (n == 2) {
+        constexpr float B[3][3] = {{0.125f, -0.5f, 0.5f}, {0.75f, 0.0f, -1.0f}, {0.125f, 0.5f, 0.5f}};
+        return B[a][p];
+    } else {
+        constexpr float B[4][4] = {{1.0f / 48.0f, -0.125f, 0.25f, -1.0f / 6.0f},
+                                   {23.0f / 48.0f, -0.625f, -0.25f, 0.5f},
+                                   {23.0f / 48.0f, 0.625f, -0.25f, -0.5f},
+                                   {1.0f / 48.0f, 0.125f, 0.25f, 1.0f / 6.0f}};
+        return B[a][p];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Per-line data of the slab form.  ir_i = 1 / r_i, or 0 when r_i == 0.
 // ---------------------------------------------------------------------------
