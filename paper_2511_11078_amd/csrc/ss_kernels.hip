@@ -201,7 +201,9 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
 // ---------------------------------------------------------------------------
 constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
-constexpr int CRAY_CAP = 512;                   // lines per LDS chunk
+constexpr int CRAY_CAP = 832;                   // lines in the LDS table
+constexpr int VIEWS_PER_BATCH = 4;              // views whose hits are integrated together
+constexpr int HITQ_CAP = 16;                    // queued hits per thread
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
 struct CellRay {     // 48 bytes
@@ -222,7 +224,7 @@ __device__ __forceinline__ void fill_cellray(CellRay &rec, const float *__restri
         // a degenerate line is put far outside every cell
         rec.a[k] = L.ok ? (float)(L.a[k] - centre[k]) : 1.0e30f;
         rec.w[k] = (float)L.w[k];
-        rec.iw[k] = rec.w[k] != 0.0f ? (float)(1.0 / L.w[k]) : 0.0f;
+        rec.iw[k] = rec.w[k] != 0.0f ? __builtin_amdgcn_rcpf(rec.w[k]) : 0.0f;
         zm |= rec.w[k] == 0.0f ? (1 << k) : 0;
     }
     rec.y = L.ok ? yval : 0.0f;
@@ -250,6 +252,54 @@ __device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], 
         }
     }
     return in && t0 < t1;
+}
+
+// Add one line's chord through the cell to the cell's moments: at the m
+// Gauss-Legendre nodes of the chord, y * weight * u1^p1 u2^p2 u3^p3 for the
+// centred cell coordinates u = t - 1/2.
+template <int n>
+__device__ __forceinline__ void integrate_hit(const CellRay &r, const float lo[3], float acc[]) {
+    using Rule = GLRule<Degree<n>::m>;
+    constexpr int NB = n + 1;
+    float t0, t1;
+    cell_chord<n>(r, lo, t0, t1);
+    const float mid = 0.5f * (t0 + t1), half = 0.5f * (t1 - t0);
+    float uc[3], du[3];  // centred cell coordinate at mid, and its step
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        uc[q] = fmaf(mid, r.w[q], r.a[q]) - (lo[q] + 0.5f);
+        du[q] = half * r.w[q];
+    }
+    const float sc = half * r.y;
+#pragma unroll
+    for (int l = 0; l < Rule::m; ++l) {
+        const float xi = Rule::x(l);
+        // powers u^p of the three centred coordinates (p >= 1)
+        float P1[NB], P2[NB], P3[NB];
+        P1[0] = Rule::w(l) * sc;  // axis 1 carries the quadrature weight
+        P2[0] = 1.0f;
+        P3[0] = 1.0f;
+        const float u1 = fmaf(du[0], xi, uc[0]), u2 = fmaf(du[1], xi, uc[1]), u3 = fmaf(du[2], xi, uc[2]);
+#pragma unroll
+        for (int p = 1; p <= n; ++p) {
+            P1[p] = P1[p - 1] * u1;
+            P2[p] = p == 1 ? u2 : P2[p - 1] * u2;
+            P3[p] = p == 1 ? u3 : P3[p - 1] * u3;
+        }
+#pragma unroll
+        for (int p2 = 0; p2 < NB; ++p2) {
+            float xy[NB];
+#pragma unroll
+            for (int p1 = 0; p1 < NB; ++p1) xy[p1] = p2 == 0 ? P1[p1] : P2[p2] * P1[p1];
+#pragma unroll
+            for (int p1 = 0; p1 < NB; ++p1) acc[p2 * NB + p1] += xy[p1];
+#pragma unroll
+            for (int p3 = 1; p3 < NB; ++p3)
+#pragma unroll
+                for (int p1 = 0; p1 < NB; ++p1)
+                    acc[(p3 * NB + p2) * NB + p1] = fmaf(P3[p3], xy[p1], acc[(p3 * NB + p2) * NB + p1]);
+        }
+    }
 }
 
 // Pixels whose centre lies in the bounding rectangle of the projected
@@ -295,8 +345,9 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
     __shared__ CellRay rays[CRAY_CAP];
+    __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of table indices
     __shared__ float2 corner[NCORNER];
-    __shared__ ViewProj vp;
+    __shared__ LocalProj lp;
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
     const int nbx = (M0 + GX - 1) / GX, nby = (M1 + GY - 1) / GY, nbz = (L + GZ - 1) / GZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -317,19 +368,24 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     float acc[NB * NB * NB];
 #pragma unroll
     for (int e = 0; e < NB * NB * NB; ++e) acc[e] = 0.0f;
+    int used = 0, nviews = 0;  // table entries and views of the current batch (block-uniform)
+    int nhit = 0;              // this thread's queued hits
 
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
-        if (tid == 0) make_viewproj(e, kind, vp);
+        if (tid == 0) {
+            ViewProj vp;
+            make_viewproj(e, kind, vp);
+            make_localproj(vp, centre, lp);
+        }
         __syncthreads();
         // detector position (pixel units) of every lattice corner of the brick
         for (int t = tid; t < NCORNER; t += blockDim.x) {
             const int cx = t % (GX + 1), cy = (t / (GX + 1)) % (GY + 1), cz = t / ((GX + 1) * (GY + 1));
-            const double X[3] = {centre[0] + (double)cx - 0.5 * GX, centre[1] + (double)cy - 0.5 * GY,
-                                 centre[2] + (double)cz - 0.5 * GZ};
-            double cc, rr;
-            corner[t] = to_detector(vp, X, cc, rr) ? make_float2((float)cc + oc, (float)rr + orow)
-                                                   : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            const float d[3] = {(float)cx - 0.5f * GX, (float)cy - 0.5f * GY, (float)cz - 0.5f * GZ};
+            float cc, rr;
+            corner[t] = local_to_detector(lp, d, cc, rr) ? make_float2(cc + oc, rr + orow)
+                                                         : make_float2(__builtin_nanf(""), __builtin_nanf(""));
         }
         __syncthreads();
         // the brick's pixel rectangle (from its eight corners, the same for
@@ -338,89 +394,55 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
         shadow_rect(corner, GX, GY, GZ, 0, 0, 0, R, C, bi0, bi1, bj0, bj1);
         int mi0 = 0, mi1 = -1, mj0 = 0, mj1 = -1;
         if (mine) shadow_rect(corner, 1, 1, 1, tx, ty, tz, R, C, mi0, mi1, mj0, mj1);
+        // the view's lines go into the table in segments of whole rows (of
+        // columns, for a row wider than the table); this cell's hits are
+        // queued and integrated when the table or the batch of views is full
         const int W = bi1 - bi0 + 1;
-        const int rows_per_chunk = W > 0 ? max(1, CRAY_CAP / W) : 1;
-        for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_chunk) {
-            const int cj1 = min(bj1, cj0 + rows_per_chunk - 1);
+        if (W > 0 && bj1 >= bj0) {
+            const int rows_per_seg = max(1, CRAY_CAP / W);
             const int cols = min(W, CRAY_CAP);
-            for (int ci0 = bi0; ci0 <= bi1; ci0 += cols) {
-                const int ci1 = min(bi1, ci0 + cols - 1);
-                const int cw = ci1 - ci0 + 1;
-                const int cn = (cj1 - cj0 + 1) * cw;
-                __syncthreads();
-                for (int t = tid; t < cn; t += blockDim.x) {
-                    const int jj = cj0 + t / cw, ii = ci0 + t % cw;
-                    fill_cellray(rays[t], e, kind, R, C, jj, ii, centre, y[((int64_t)v * R + jj) * C + ii]);
-                }
-                __syncthreads();
-                const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
-                const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
-                const int nw = i1 - i0 + 1;
-                const int ncand = (nw > 0 && j1 >= j0) ? nw * (j1 - j0 + 1) : 0;
-                for (int base = 0; base < ncand; base += 32) {
-                    // mark the candidates whose chord through the cell is non-empty
-                    uint32_t hits = 0;
-                    const int cnt = min(32, ncand - base);
-                    int jr = base / nw, ir = base - jr * nw;
-                    for (int k = 0; k < cnt; ++k) {
-                        const CellRay &r = rays[(j0 + jr - cj0) * cw + (i0 + ir - ci0)];
-                        float t0, t1;
-                        if (cell_chord<n>(r, lo, t0, t1)) hits |= 1u << k;
-                        if (++ir == nw) { ir = 0; ++jr; }
+            for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_seg) {
+                const int cj1 = min(bj1, cj0 + rows_per_seg - 1);
+                for (int ci0 = bi0; ci0 <= bi1; ci0 += cols) {
+                    const int ci1 = min(bi1, ci0 + cols - 1);
+                    const int cw = ci1 - ci0 + 1;
+                    const int cn = (cj1 - cj0 + 1) * cw;
+                    if (used + cn > CRAY_CAP || nviews == VIEWS_PER_BATCH) {
+                        for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
+                        nhit = 0;
+                        used = 0;
+                        nviews = 0;
                     }
-                    // integrate those
-                    while (hits) {
-                        const int k = __builtin_ctz(hits);
-                        hits &= hits - 1u;
-                        const int idx = base + k;
-                        const int jr = idx / nw;
-                        const CellRay &r = rays[(j0 + jr - cj0) * cw + (i0 + idx - jr * nw - ci0)];
-                        float t0, t1;
-                        cell_chord<n>(r, lo, t0, t1);
-                        const float mid = 0.5f * (t0 + t1), half = 0.5f * (t1 - t0);
-                        float uc[3], du[3];  // centred cell coordinate at mid, and its step
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            uc[q] = fmaf(mid, r.w[q], r.a[q]) - (lo[q] + 0.5f);
-                            du[q] = half * r.w[q];
-                        }
-                        const float sc = half * r.y;
-#pragma unroll
-                        for (int l = 0; l < Rule::m; ++l) {
-                            const float xi = Rule::x(l);
-                            // powers u^p of the three centred coordinates (p >= 1)
-                            float P1[NB], P2[NB], P3[NB];
-                            P1[0] = Rule::w(l) * sc;  // axis 1 carries the quadrature weight
-                            P2[0] = 1.0f;
-                            P3[0] = 1.0f;
-                            const float u1 = fmaf(du[0], xi, uc[0]), u2 = fmaf(du[1], xi, uc[1]),
-                                        u3 = fmaf(du[2], xi, uc[2]);
-#pragma unroll
-                            for (int p = 1; p <= n; ++p) {
-                                P1[p] = P1[p - 1] * u1;
-                                P2[p] = p == 1 ? u2 : P2[p - 1] * u2;
-                                P3[p] = p == 1 ? u3 : P3[p - 1] * u3;
-                            }
-#pragma unroll
-                            for (int p2 = 0; p2 < NB; ++p2) {
-                                float xy[NB];
-#pragma unroll
-                                for (int p1 = 0; p1 < NB; ++p1) xy[p1] = p2 == 0 ? P1[p1] : P2[p2] * P1[p1];
-#pragma unroll
-                                for (int p1 = 0; p1 < NB; ++p1) acc[p2 * NB + p1] += xy[p1];
-#pragma unroll
-                                for (int p3 = 1; p3 < NB; ++p3)
-#pragma unroll
-                                    for (int p1 = 0; p1 < NB; ++p1)
-                                        acc[(p3 * NB + p2) * NB + p1] =
-                                            fmaf(P3[p3], xy[p1], acc[(p3 * NB + p2) * NB + p1]);
+                    __syncthreads();
+                    for (int t = tid; t < cn; t += blockDim.x) {
+                        const int jj = cj0 + t / cw, ii = ci0 + t % cw;
+                        fill_cellray(rays[used + t], e, kind, R, C, jj, ii, centre,
+                                     y[((int64_t)v * R + jj) * C + ii]);
+                    }
+                    __syncthreads();
+                    const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
+                    const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
+                    for (int jj = j0; jj <= j1; ++jj)
+                        for (int ii = i0; ii <= i1; ++ii) {
+                            const int idx = used + (jj - cj0) * cw + (ii - ci0);
+                            float t0, t1;
+                            if (cell_chord<n>(rays[idx], lo, t0, t1)) {
+                                if (nhit == HITQ_CAP) {  // queue full: integrate it now
+                                    for (int k = 0; k < nhit; ++k)
+                                        integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
+                                    nhit = 0;
+                                }
+                                hitq[nhit * 256 + tid] = (unsigned short)idx;
+                                ++nhit;
                             }
                         }
-                    }
+                    used += cn;
                 }
             }
+            ++nviews;
         }
     }
+    for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
     // moments -> per-basis integrals: apply the blending map along each axis
     if constexpr (n > 0) {
 #pragma unroll

@@ -82,6 +82,56 @@ __device__ __forceinline__ void make_viewproj(const float *__restrict__ e, int k
     }
 }
 
+// Detector coordinates of points X = c + delta near a centre c, evaluated in
+// FP32 for small delta; every term that involves c or the source is formed
+// in FP64 once.  With D = c - s (cone) or c - d0 (parallel):
+//   parallel: col = D . du_s + delta . du_s
+//   cone:     col = (s - d0) . du_s + plane (D . du_s + delta . du_s) / (D . nrm + delta . nrm)
+// and likewise for rows with dv_s.
+struct LocalProj {
+    float du[3], dv[3], nm[3];
+    float nc, nr, dn;   // D . du_s, D . dv_s, D . nrm
+    float ac, ar;       // (s - d0) . du_s, (s - d0) . dv_s  (cone)
+    float plane;
+    int kind;
+};
+
+__device__ __forceinline__ void make_localproj(const ViewProj &P, const double c[3], LocalProj &L) {
+    double D[3], sd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        D[k] = c[k] - (P.kind == 0 ? P.d0[k] : P.s[k]);
+        sd[k] = P.s[k] - P.d0[k];
+        L.du[k] = (float)P.du_s[k];
+        L.dv[k] = (float)P.dv_s[k];
+        L.nm[k] = (float)P.nrm[k];
+    }
+    L.nc = (float)(D[0] * P.du_s[0] + D[1] * P.du_s[1] + D[2] * P.du_s[2]);
+    L.nr = (float)(D[0] * P.dv_s[0] + D[1] * P.dv_s[1] + D[2] * P.dv_s[2]);
+    L.dn = (float)(D[0] * P.nrm[0] + D[1] * P.nrm[1] + D[2] * P.nrm[2]);
+    L.ac = (float)(sd[0] * P.du_s[0] + sd[1] * P.du_s[1] + sd[2] * P.du_s[2]);
+    L.ar = (float)(sd[0] * P.dv_s[0] + sd[1] * P.dv_s[1] + sd[2] * P.dv_s[2]);
+    L.plane = (float)P.plane;
+    L.kind = P.kind;
+}
+
+// false when X is on or behind the source plane (cone)
+__device__ __forceinline__ bool local_to_detector(const LocalProj &L, const float d[3], float &col, float &row) {
+    const float nu = fmaf(d[2], L.du[2], fmaf(d[1], L.du[1], fmaf(d[0], L.du[0], L.nc)));
+    const float nv = fmaf(d[2], L.dv[2], fmaf(d[1], L.dv[1], fmaf(d[0], L.dv[0], L.nr)));
+    if (L.kind == 0) {
+        col = nu;
+        row = nv;
+        return true;
+    }
+    const float den = fmaf(d[2], L.nm[2], fmaf(d[1], L.nm[1], fmaf(d[0], L.nm[0], L.dn)));
+    if (!(den * L.plane > 0.0f)) return false;
+    const float lam = L.plane * __builtin_amdgcn_rcpf(den);
+    col = fmaf(lam, nu, L.ac);
+    row = fmaf(lam, nv, L.ar);
+    return true;
+}
+
 // Pixel rectangle [i0, i1] x [j0, j1] covering every line that meets the
 // box [lo, hi] (whole detector if the projection is undefined).
 __device__ __forceinline__ void box_to_pixels(const ViewProj &P, const double lo[3], const double hi[3], int R,
