@@ -142,6 +142,39 @@ def test_backproject_all_coefficients(ctxs, n, kind):
     assert e <= (TOL if n > 0 else 1e-4)
 
 
+@pytest.mark.parametrize("case", ["cone_fine_pitch", "parallel_wide_rows"])
+def test_backproject_large_shadows(ctxs, case):
+    """Detector pixels much smaller than a knot cell: a brick's shadow holds
+    more lines than the LDS table (rows split into segments; in the second
+    case a single row is wider than the table, so columns split too) and a
+    cell is hit by far more lines per view than a thread queues at once."""
+    say(f"backproject large shadows: {case}")
+    rng = np.random.default_rng(245)
+    if case == "cone_fine_pitch":
+        dims = (17, 15, 11)
+        geom = synth.cone_circular_geometry(3, 150, 170, src_radius=40.0, src_det=60.0, pitch=0.16, angle0=0.3)
+    else:
+        # columns along the diagonal of the x1-x2 plane, so that an 8 x 8
+        # brick spans all 900 columns (more than the table holds)
+        dims = (9, 5, 4)
+        vecs = []
+        for tilt in (0.1, -0.07):
+            w = np.array([tilt, 0.05, 1.0])
+            w /= np.linalg.norm(w)
+            u = np.array([1.0, 1.0, 0.0])
+            u -= (u @ w) * w
+            u /= np.linalg.norm(u)
+            vecs.append(np.concatenate([w, np.zeros(3), 0.012 * u, 0.012 * np.cross(w, u)]))
+        geom = synth.Geometry("parallel", 2, 40, 900, np.asarray(vecs, dtype=np.float32))
+    y = rng.standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32)
+    coefs = synth.sample_indices(int(np.prod(dims)), 120, seed=247)
+    got = to_np(ctxs[3].backproject(to_gpu(y), geom, dims)).ravel()[coefs]
+    want = oracle.backproject_subset(y, geom, dims, 3, coefs=coefs)
+    e = rel_l2(got, want)
+    say(f"  rel-L2 {e:.3e} over {coefs.size} coefficients")
+    assert np.abs(want).max() > 0 and e <= TOL
+
+
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
 def test_dot_product_test(ctxs, kind):
     say(f"dot test {kind}")
