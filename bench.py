@@ -56,8 +56,14 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "9b2cdf2431957a0235ec12f49b09f35b1a76c4f842c38e2b8f6ce86c8ef6ea32"
+TRAFFIC_SHA256 = "29bb69e28ed9140459247726fdf27d345004b3bf49714983f1ac0a57e726b91c"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
+    ("project_kernel", 3): (2.0 * 46273200 * 1024, 1.0 * 279445 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3040053 * 1024, 1.0 * 6584390 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2477744 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 0): (2.0 * 45138615 * 1024, 1.0 * 258547 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1207467 * 1024, 1.0 * 67199 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32791 * 1024, 1.0 * 65536 * 1024),
 }
 
 
@@ -215,7 +221,7 @@ def main():
         out["rel_l2_vs_oracle"] = rel[main_form]
         # algorithmic work (oracle counts on 4,096 of the sampled lines):
         # (line, basis) pairs and their footprint segments, and knot cells per line
-        cnt_rays = ys[:4096]
+        cnt_rays = ys[:: max(1, ys.size // 4096)][:4096]  # spread over all views (ys is sorted)
         pairs, segs = oracle.counts(dims, geom, n, rays=cnt_rays)
         cells = oracle.direct_counts(dims, geom, n, rays=cnt_rays)
         pairs_per_ray = float(pairs.mean())
