@@ -123,7 +123,13 @@ ss_status ss_project(ss_ctx *ctx, const float *d_coeffs, const int64_t dims[3],
 
 /* Adjoint (exact transpose of ss_project up to FP32 rounding):
  * d_coeffs[k] = sum over lines m of d_sino[m] * P phi(w_m, s_m - Proj k),
- * overwritten.  Same layouts and errors as ss_project. */
+ * overwritten.  Same layouts and errors as ss_project.
+ * With SS_FORM_QUAD_FP32 the context keeps a device table of (degree+1)^3
+ * floats per knot cell of the support-padded volume (4.45 GB for 256^3,
+ * degree 3), allocated on the first call that needs it and at most 8 GiB
+ * (larger volumes are processed in z-chunks); growing it waits for the
+ * device.  Calls on one context must not overlap in time (they share the
+ * table).  Additional error: SS_ENOMEM when the table cannot be allocated. */
 ss_status ss_backproject(ss_ctx *ctx, const float *d_sino, const ss_geometry *geom,
                          const int64_t dims[3], float *d_coeffs, void *hip_stream);
 
