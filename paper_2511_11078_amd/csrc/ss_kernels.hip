@@ -13,6 +13,13 @@
 
 namespace ss {
 
+// Forward launch: one 256-thread block per 16x16-pixel tile and view; tiles
+// are grouped into FT_SH x FT_SW super-tiles (padded at the detector edge).
+constexpr int FT_SH = 2, FT_SW = 4;
+__host__ __device__ inline int fwd_tile_slots(int tR, int tC) {
+    return ((tR + FT_SH - 1) / FT_SH) * ((tC + FT_SW - 1) / FT_SW) * FT_SH * FT_SW;
+}
+
 // ---------------------------------------------------------------------------
 // Forward, quadrature form: cell walk.  The footprint of a basis is the sum,
 // over the knot cells its support spans, of the Gauss-Legendre integral of
@@ -34,9 +41,18 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
     constexpr double kap = (double)Degree<n>::kap;
     constexpr int qoff = CellBasis<n>::qoff;
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
-    const int nblocks = V * tR * tC;
+    const int nblocks = V * fwd_tile_slots(tR, tC);
+    // block order: views innermost, then the 16x16-pixel tiles of an
+    // FT_SH x FT_SW super-tile, then super-tiles; each XCD gets a contiguous
+    // run, so the lines its CUs walk at one time come from neighbouring
+    // pixels of consecutive views and share coefficient lines in its L2
     const int b = xcd_remap(blockIdx.x, nblocks);
-    const int v = b / (tR * tC), rem = b % (tR * tC);
+    const int v = b % V, t = b / V;
+    const int sC = (tC + FT_SW - 1) / FT_SW;
+    const int st = t / (FT_SH * FT_SW), q = t % (FT_SH * FT_SW);
+    const int tr = (st / sC) * FT_SH + q / FT_SW, tc = (st % sC) * FT_SW + q % FT_SW;
+    if (tr >= tR || tc >= tC) return;  // padding slot of a partial super-tile
+    const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int i = (rem % tC) * 16 + (wave & 1) * 8 + (lane & 7);
@@ -617,7 +633,7 @@ __global__ void xpay_kernel(const double *__restrict__ beta, const float *__rest
 template <int n>
 static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     const int tR = (a.R + 15) / 16, tC = (a.C + 15) / 16;
-    const int nb = a.V * tR * tC;
+    const int nb = a.V * fwd_tile_slots(tR, tC);
     hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1], a.N[2], a.geom,
                        a.kind, a.V, a.R, a.C, a.sino);
     return hipGetLastError();
