@@ -201,13 +201,16 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
 // fixed.
 //
 // Pass 1 blocks own GX x GY x GZ bricks of cells.  Per view a block projects
-// the brick's lattice corners once (FP64) into LDS, sets the lines of the
-// brick's pixel rectangle up once (FP64, anchor re-based at the brick centre)
-// into an LDS table, and every thread takes the bounding rectangle of its
-// own cell's eight projected corners as its candidate pixels: first it marks
-// the candidates whose chord through the cell is non-empty, then it
-// integrates only those, so the wave runs as many integration rounds as its
-// busiest lane has hits rather than as it has candidates.
+// the brick's lattice corners once into LDS (FP32 offsets from the brick
+// centre, every term involving the centre or the source formed in FP64),
+// appends the lines of the brick's pixel rectangle to an LDS table (FP64
+// set-up, anchor re-based at the brick centre), and every thread takes the
+// bounding rectangle of its own cell's eight projected corners as its
+// candidate pixels.  A thread queues the candidates whose chord through its
+// cell is non-empty and integrates its queue once the table holds
+// VIEWS_PER_BATCH views (or is full): the wave then runs as many integration
+// rounds as its busiest lane has hits over the whole batch, not over each
+// view, and never spends a round on a candidate that misses.
 //
 // The cell table T holds (n+1)^3 FP32 entries per cell, entry-major
 // (T[a * cells + K], K x-fastest over the cells of a z-chunk), so that both
@@ -218,34 +221,29 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
 constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
 constexpr int CRAY_CAP = 832;                   // lines in the LDS table
-constexpr int VIEWS_PER_BATCH = 4;              // views whose hits are integrated together
-constexpr int HITQ_CAP = 16;                    // queued hits per thread
+constexpr int VIEWS_PER_BATCH = 8;              // views whose hits are integrated together
+constexpr int HITQ_CAP = 32;                    // queued hits per thread
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
-struct CellRay {     // 48 bytes
+struct __attribute__((aligned(8))) CellRay {  // 40 bytes
     float a[3];      // point of the line nearest the brick centre, relative to it
+    float iw[3];     // 1 / w_k; 0 marks an axis the line is parallel to
     float w[3];      // unit direction
-    float iw[3];     // 1 / w_k, 0 where w_k == 0
     float y;         // sinogram value
-    int zmask;       // bit k set: w_k == 0
-    int pad;
 };
 
 __device__ __forceinline__ void fill_cellray(CellRay &rec, const float *__restrict__ e, int kind, int R, int C, int j,
                                              int i, const double centre[3], float yval) {
     const LineD L = make_line(e, kind, R, C, j, i, centre);
-    int zm = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        // a degenerate line is put far outside every cell
+        // a degenerate line is put far outside every cell, parallel to all axes
+        const float wk = L.ok ? (float)L.w[k] : 0.0f;
         rec.a[k] = L.ok ? (float)(L.a[k] - centre[k]) : 1.0e30f;
-        rec.w[k] = (float)L.w[k];
-        rec.iw[k] = rec.w[k] != 0.0f ? __builtin_amdgcn_rcpf(rec.w[k]) : 0.0f;
-        zm |= rec.w[k] == 0.0f ? (1 << k) : 0;
+        rec.w[k] = wk;
+        rec.iw[k] = wk != 0.0f ? __builtin_amdgcn_rcpf(wk) : 0.0f;
     }
     rec.y = L.ok ? yval : 0.0f;
-    rec.zmask = L.ok ? zm : 7;
-    rec.pad = 0;
 }
 
 // Chord [t0, t1] of a line through the cell [lo, lo + 1]^3 (coordinates
@@ -259,7 +257,7 @@ __device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], 
     t1 = 3.0e38f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (r.zmask & (1 << k)) {
+        if (r.iw[k] == 0.0f) {
             in = in && (n == 0 ? lo[k] < r.a[k] : lo[k] <= r.a[k]) && r.a[k] < lo[k] + 1.0f;
         } else {
             const float ta = (lo[k] - r.a[k]) * r.iw[k], tb = (lo[k] + 1.0f - r.a[k]) * r.iw[k];
