@@ -56,14 +56,14 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "29bb69e28ed9140459247726fdf27d345004b3bf49714983f1ac0a57e726b91c"
+TRAFFIC_SHA256 = "74e39fa9ddc5f4f4f352fa9bb60834f8fc3c319c08b165e13e416cdf7cacc4c5"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("project_kernel", 3): (2.0 * 46273200 * 1024, 1.0 * 279445 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3040053 * 1024, 1.0 * 6584390 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2477744 * 1024, 1.0 * 65536 * 1024),
-    ("project_kernel", 0): (2.0 * 45138615 * 1024, 1.0 * 258547 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1207467 * 1024, 1.0 * 67199 * 1024),
-    ("cells_to_coeffs_kernel", 0): (2.0 * 32791 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 3): (2.0 * 1263418 * 1024, 1.0 * 238736 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 2986507 * 1024, 1.0 * 5732001 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2475118 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 0): (2.0 * 970820 * 1024, 1.0 * 246110 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1216239 * 1024, 1.0 * 67048 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32790 * 1024, 1.0 * 65536 * 1024),
 }
 
 

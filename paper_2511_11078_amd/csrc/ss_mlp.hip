@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
                         const float u2 = fmaf(t, rr.r2, pick3(rr.a, i2x)) - pick3(xq, i2x);
                         Slopes S;
                         S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
-                        if (chord_nonempty<n>(S, u1, u2) && rr.y != 0.0f) {
+                        if (chord_nonempty<n>(S, u1, u2)) {
                             have = true;
                             yv = rr.y;
                             const float x0 = rr.a[0] - xq[0], x1 = rr.a[1] - xq[1], x2 = rr.a[2] - xq[2];
