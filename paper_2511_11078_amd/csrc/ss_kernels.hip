@@ -13,11 +13,15 @@
 
 namespace ss {
 
-// Forward launch: one 256-thread block per 16x16-pixel tile and view; tiles
-// are grouped into FT_SH x FT_SW super-tiles (padded at the detector edge).
-constexpr int FT_SH = 2, FT_SW = 4;
-__host__ __device__ inline int fwd_tile_slots(int tR, int tC) {
-    return ((tR + FT_SH - 1) / FT_SH) * ((tC + FT_SW - 1) / FT_SW) * FT_SH * FT_SW;
+// Forward launch: one 256-thread block per 16x16-pixel tile and view.  Tiles
+// form FT_GH x FT_GW groups; groups go round-robin to the 8 XCDs (hardware
+// block h runs on XCD h % 8), and within a group the views are innermost.
+constexpr int FT_GH = 2, FT_GW = 2;
+__host__ __device__ inline int fwd_groups(int tR, int tC) {
+    return ((tR + FT_GH - 1) / FT_GH) * ((tC + FT_GW - 1) / FT_GW);
+}
+__host__ __device__ inline int64_t fwd_blocks(int tR, int tC, int V) {
+    return (int64_t)((fwd_groups(tR, tC) + 7) / 8 * 8) * FT_GH * FT_GW * V;
 }
 
 // ---------------------------------------------------------------------------
@@ -41,17 +45,19 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
     constexpr double kap = (double)Degree<n>::kap;
     constexpr int qoff = CellBasis<n>::qoff;
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
-    const int nblocks = V * fwd_tile_slots(tR, tC);
-    // block order: views innermost, then the 16x16-pixel tiles of an
-    // FT_SH x FT_SW super-tile, then super-tiles; each XCD gets a contiguous
-    // run, so the lines its CUs walk at one time come from neighbouring
-    // pixels of consecutive views and share coefficient lines in its L2
-    const int b = xcd_remap(blockIdx.x, nblocks);
-    const int v = b % V, t = b / V;
-    const int sC = (tC + FT_SW - 1) / FT_SW;
-    const int st = t / (FT_SH * FT_SW), q = t % (FT_SH * FT_SW);
-    const int tr = (st / sC) * FT_SH + q / FT_SW, tc = (st % sC) * FT_SW + q % FT_SW;
-    if (tr >= tR || tc >= tC) return;  // padding slot of a partial super-tile
+    // hardware block h runs on XCD h % 8: that XCD takes tile groups
+    // x, x + 8, x + 16, ... (spread over the detector, so the XCDs get equal
+    // work), each group for all views with the views innermost, so that the
+    // blocks it runs at one time walk neighbouring lines of consecutive
+    // views and share coefficient lines in its L2
+    const int per = FT_GH * FT_GW * V;
+    const int x = blockIdx.x % 8, l = blockIdx.x / 8;
+    const int G = (l / per) * 8 + x, inner = l % per;
+    const int v = inner % V, q = inner / V;
+    if (G >= fwd_groups(tR, tC)) return;  // padding group
+    const int gC = (tC + FT_GW - 1) / FT_GW;
+    const int tr = (G / gC) * FT_GH + q / FT_GW, tc = (G % gC) * FT_GW + q % FT_GW;
+    if (tr >= tR || tc >= tC) return;  // padding tile of an edge group
     const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);
@@ -631,7 +637,7 @@ __global__ void xpay_kernel(const double *__restrict__ beta, const float *__rest
 template <int n>
 static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     const int tR = (a.R + 15) / 16, tC = (a.C + 15) / 16;
-    const int nb = a.V * fwd_tile_slots(tR, tC);
+    const int nb = (int)fwd_blocks(tR, tC, a.V);
     hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1], a.N[2], a.geom,
                        a.kind, a.V, a.R, a.C, a.sino);
     return hipGetLastError();
