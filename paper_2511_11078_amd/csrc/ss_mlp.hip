@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__rest
 // ---------------------------------------------------------------------------
 constexpr int MBX = 8, MBY = 8, MBZ = 4;
 constexpr int MRAY_CAP = 384;
+constexpr float MPIX_MARGIN = 1.0e-3f;  // pixels
 
 struct RayRecM {     // 80 bytes
     float a[3];      // point of the line nearest the brick centre, relative to it
@@ -437,8 +438,10 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
     __shared__ MlpImage Wt;
     __shared__ RayRecM rays[MRAY_CAP];
     __shared__ ViewProj vp;
+    __shared__ LocalProj lp;
     __shared__ int sbox[4];
     load_image(Wt, img);
+    constexpr float hf = Degree<n>::h;
     const int nbx = (N0 + MBX - 1) / MBX, nby = (N1 + MBY - 1) / MBY, nbz = (N2 + MBZ - 1) / MBZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
@@ -457,6 +460,7 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
         __syncthreads();
         if (tid == 0) {
             make_viewproj(e, kind, vp);
+            make_localproj(vp, centre, lp);
             double lo[3], hi[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -470,13 +474,32 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
         const int bi0 = sbox[0], bi1 = sbox[1], bj0 = sbox[2], bj1 = sbox[3];
         int mi0 = 0, mi1 = -1, mj0 = 0, mj1 = -1;
         if (mine) {
-            double lo[3], hi[3];
+            // the pixels whose centre lies in the bounding rectangle of the
+            // projected corners of this coefficient's support box (FP32
+            // offsets from the brick centre; MPIX_MARGIN covers the rounding)
+            float cmin = 3.0e38f, cmax = -3.0e38f, rmin = 3.0e38f, rmax = -3.0e38f;
+            bool bad = false;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = centre[k] + (double)xq[k] - h;
-                hi[k] = centre[k] + (double)xq[k] + h;
+            for (int k = 0; k < 8; ++k) {
+                const float d[3] = {xq[0] + ((k & 1) ? hf : -hf), xq[1] + ((k & 2) ? hf : -hf),
+                                    xq[2] + ((k & 4) ? hf : -hf)};
+                float cc, rr;
+                if (!local_to_detector(lp, d, cc, rr)) bad = true;
+                cmin = fminf(cmin, cc); cmax = fmaxf(cmax, cc);
+                rmin = fminf(rmin, rr); rmax = fmaxf(rmax, rr);
             }
-            box_to_pixels(vp, lo, hi, R, C, mi0, mi1, mj0, mj1);
+            const float oc = 0.5f * (float)(C - 1), orow = 0.5f * (float)(R - 1);
+            if (bad) {
+                mi0 = 0; mi1 = C - 1; mj0 = 0; mj1 = R - 1;
+            } else {
+                const float fi0 = fmaxf(ceilf(cmin + oc - MPIX_MARGIN), 0.0f);
+                const float fi1 = fminf(floorf(cmax + oc + MPIX_MARGIN), (float)(C - 1));
+                const float fj0 = fmaxf(ceilf(rmin + orow - MPIX_MARGIN), 0.0f);
+                const float fj1 = fminf(floorf(rmax + orow + MPIX_MARGIN), (float)(R - 1));
+                if (fi0 <= fi1 && fj0 <= fj1) {
+                    mi0 = (int)fi0; mi1 = (int)fi1; mj0 = (int)fj0; mj1 = (int)fj1;
+                }
+            }
         }
         const int W = bi1 - bi0 + 1;
         const int rows_per_chunk = W > 0 ? max(1, MRAY_CAP / W) : 1;
