@@ -29,7 +29,7 @@ struct ss_ctx {
     std::vector<float> last_vecs;   // host copy of what d_geom holds
     double *d_partials = nullptr;   // dot-product partial sums
     void *d_mlp = nullptr;          // network weights in kernel layout
-    float *d_cells = nullptr;       // knot-cell table of the quadrature adjoint
+    float *d_cells = nullptr;       // quadrature scratch: padded coefficients (forward), knot-cell table (adjoint)
     int64_t cells_cap = 0;          // floats
 };
 
@@ -171,7 +171,8 @@ ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
     return SS_OK;
 }
 
-// Make the knot-cell table hold at least `need` floats.
+// Make the quadrature scratch (padded coefficients for the forward, the
+// knot-cell table for the adjoint) hold at least `need` floats.
 ss_status ensure_cells(ss_ctx *ctx, int64_t need) {
     if (need <= ctx->cells_cap) return SS_OK;
     hipError_t e;
@@ -184,7 +185,7 @@ ss_status ensure_cells(ss_ctx *ctx, int64_t need) {
     }
     if ((e = hipMalloc(&ctx->d_cells, (size_t)need * sizeof(float))) != hipSuccess) {
         ctx->d_cells = nullptr;
-        return fail(SS_ENOMEM, "knot-cell table (%lld bytes): %s", (long long)need * 4, hipGetErrorString(e));
+        return fail(SS_ENOMEM, "quadrature scratch (%lld bytes): %s", (long long)need * 4, hipGetErrorString(e));
     }
     ctx->cells_cap = need;
     return SS_OK;
@@ -302,6 +303,11 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
     if (forward) {
         a.coeffs = in;
         a.sino = out;
+        if (ctx->form == SS_FORM_QUAD_FP32) {
+            if (ss_status s = ensure_cells(ctx, ss::project_quad_scratch_floats(ctx->degree, a.N))) return s;
+            a.scratch = ctx->d_cells;
+            a.scratch_floats = ctx->cells_cap;
+        }
         e = ctx->form == SS_FORM_QUAD_FP32 ? ss::launch_project_quad(ctx->degree, a, st)
                                            : ss::launch_project_mlp(ctx->degree, a, st);
     } else {

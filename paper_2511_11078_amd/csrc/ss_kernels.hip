@@ -24,6 +24,23 @@ __host__ __device__ inline int64_t fwd_blocks(int tR, int tC, int V) {
     return (int64_t)((fwd_groups(tR, tC) + 7) / 8 * 8) * FT_GH * FT_GW * V;
 }
 
+// Zero-padded copy of the coefficients for the forward walk: FWD_PAD(n)
+// zero layers on every side, so that the (n+1)^3 block of every knot cell of
+// the support-padded box (and of one cell beyond) is inside the copy.
+__global__ void __launch_bounds__(256) pad_volume_kernel(const float *__restrict__ c, int N0, int N1, int N2, int P,
+                                                         float *__restrict__ out) {
+    const int S0 = N0 + 2 * P, S1 = N1 + 2 * P, S2 = N2 + 2 * P;
+    const int64_t total = (int64_t)S0 * S1 * S2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int x = (int)(i % S0) - P;
+        const int64_t r = i / S0;
+        const int yy = (int)(r % S1) - P, z = (int)(r / S1) - P;
+        const bool in = x >= 0 && x < N0 && yy >= 0 && yy < N1 && z >= 0 && z < N2;
+        out[i] = in ? c[((int64_t)z * N1 + yy) * N0 + x] : 0.0f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Forward, quadrature form: cell walk.  The footprint of a basis is the sum,
 // over the knot cells its support spans, of the Gauss-Legendre integral of
@@ -36,7 +53,7 @@ __host__ __device__ inline int64_t fwd_blocks(int tR, int tC, int V) {
 // with the node positions and per-axis weights shared by the (n+1)^3 bases.
 // ---------------------------------------------------------------------------
 template <int n>
-__global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ c, int N0, int N1, int N2,
+__global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict__ cp, int N0, int N1, int N2,
                                                       const float *__restrict__ geom, int kind, int V, int R,
                                                       int C, float *__restrict__ y) {
     using Rule = GLRule<Degree<n>::m>;
@@ -110,7 +127,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
                     tmax[k] = 1e300;
                 }
             }
-            const int64_t s1 = N0, s2 = (int64_t)N0 * N1;
+            // zero-padded copy of the coefficients (FWD_PAD(n) layers per side)
+            constexpr int P = FWD_PAD(n);
+            const int64_t s1 = N0 + 2 * P, s2 = (int64_t)(N0 + 2 * P) * (N1 + 2 * P);
+            const int hi0 = N0 - 1 + P - n, hi1 = N1 - 1 + P - n, hi2 = N2 - 1 + P - n;
             double tc = t0;
             // every step moves one axis to its next knot plane: the walk ends
             // after at most sum_k (N_k + 2h + 2) steps
@@ -130,29 +150,21 @@ __global__ void __launch_bounds__(256) project_kernel(const float *__restrict__ 
                         dl[k] = (float)(half * L.w[k]);
                         q0[k] = m[k] + qoff;
                     }
-                    // coefficient block (zero outside the volume)
+                    // coefficient block from the padded copy: every cell of the
+                    // walk lies in the support-padded box, so its block is inside
+                    // the copy (the clamp only guards a cell index rounded past
+                    // the box edge, whose segment has no length)
                     float cb[NB][NB][NB];
-                    const bool inner = q0[0] >= 0 && q0[0] + n < N0 && q0[1] >= 0 && q0[1] + n < N1 &&
-                                       q0[2] >= 0 && q0[2] + n < N2;
-                    if (inner) {
-                        const float *base = c + (int64_t)q0[2] * s2 + (int64_t)q0[1] * s1 + q0[0];
+                    {
+                        const int x0 = min(max(q0[0], -P), hi0) + P, x1 = min(max(q0[1], -P), hi1) + P,
+                                  x2 = min(max(q0[2], -P), hi2) + P;
+                        const float *base = cp + (int64_t)x2 * s2 + (int64_t)x1 * s1 + x0;
 #pragma unroll
                         for (int a3 = 0; a3 < NB; ++a3)
 #pragma unroll
                             for (int a2 = 0; a2 < NB; ++a2)
 #pragma unroll
                                 for (int a1 = 0; a1 < NB; ++a1) cb[a3][a2][a1] = base[a3 * s2 + a2 * s1 + a1];
-                    } else {
-#pragma unroll
-                        for (int a3 = 0; a3 < NB; ++a3)
-#pragma unroll
-                            for (int a2 = 0; a2 < NB; ++a2)
-#pragma unroll
-                                for (int a1 = 0; a1 < NB; ++a1) {
-                                    const int k1 = q0[0] + a1, k2 = q0[1] + a2, k3 = q0[2] + a3;
-                                    const bool ok = k1 >= 0 && k1 < N0 && k2 >= 0 && k2 < N1 && k3 >= 0 && k3 < N2;
-                                    cb[a3][a2][a1] = ok ? c[(int64_t)k3 * s2 + (int64_t)k2 * s1 + k1] : 0.0f;
-                                }
                     }
                     float seg = 0.0f;
 #pragma unroll
@@ -638,9 +650,20 @@ template <int n>
 static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     const int tR = (a.R + 15) / 16, tC = (a.C + 15) / 16;
     const int nb = (int)fwd_blocks(tR, tC, a.V);
-    hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1], a.N[2], a.geom,
+    constexpr int P = FWD_PAD(n);
+    const int64_t padded = (int64_t)(a.N[0] + 2 * P) * (a.N[1] + 2 * P) * (a.N[2] + 2 * P);
+    if (!a.scratch || a.scratch_floats < padded) return hipErrorInvalidValue;
+    const int pb = (int)std::min<int64_t>((padded + 255) / 256, 65536);
+    hipLaunchKernelGGL(pad_volume_kernel, dim3(pb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1], a.N[2], P,
+                       a.scratch);
+    hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), 0, st, a.scratch, a.N[0], a.N[1], a.N[2], a.geom,
                        a.kind, a.V, a.R, a.C, a.sino);
     return hipGetLastError();
+}
+
+int64_t project_quad_scratch_floats(int degree, const int N[3]) {
+    const int64_t P = degree + 1;
+    return (N[0] + 2 * P) * (N[1] + 2 * P) * (N[2] + 2 * P);
 }
 
 int64_t backproject_quad_scratch_floats(int degree, const int N[3]) {

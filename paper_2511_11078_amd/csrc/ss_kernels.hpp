@@ -33,7 +33,7 @@ struct LaunchArgs {
     int N[3];
     int kind, V, R, C;
     const void *mlp;       // device weights (network form)
-    float *scratch;        // quadrature adjoint: knot-cell table
+    float *scratch;        // quadrature forward: padded coefficients; adjoint: knot-cell table
     int64_t scratch_floats;
 };
 
@@ -42,6 +42,9 @@ struct LaunchArgs {
 constexpr int64_t CELL_SCRATCH_FLOATS = (int64_t)1 << 31;
 // Table size the quadrature adjoint uses for a volume of N[0] x N[1] x N[2].
 int64_t backproject_quad_scratch_floats(int degree, const int N[3]);
+// Zero-padded copy of the coefficients the quadrature forward walks.
+#define FWD_PAD(n) ((n) + 1)
+int64_t project_quad_scratch_floats(int degree, const int N[3]);
 
 hipError_t launch_project_quad(int degree, const LaunchArgs &a, hipStream_t st);
 hipError_t launch_backproject_quad(int degree, const LaunchArgs &a, hipStream_t st);
