@@ -116,8 +116,11 @@ ss_status ss_destroy(ss_ctx *ctx);
 /* Forward transform, eq. (7): d_sino[v][j][i] = sum_k c_k P phi(w, s - Proj k)
  * for every pixel line.  d_coeffs: FP32 [dims[2]][dims[1]][dims[0]];
  * d_sino: FP32 [n_views][det_rows][det_cols], overwritten.
+ * With SS_FORM_QUAD_FP32 the context's device scratch (the one described
+ * at ss_backproject) first receives a zero-padded copy of d_coeffs,
+ * (dims + 2 degree + 2) floats per axis.
  * Errors: SS_EINVAL (null pointers, dims < 1 or > 4096, non-finite vecs,
- * zero-length ray direction, more than 2^31 rays per call). */
+ * zero-length ray direction, more than 2^31 rays per call), SS_ENOMEM. */
 ss_status ss_project(ss_ctx *ctx, const float *d_coeffs, const int64_t dims[3],
                      const ss_geometry *geom, float *d_sino, void *hip_stream);
 
