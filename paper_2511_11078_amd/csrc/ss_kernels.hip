@@ -13,17 +13,6 @@
 
 namespace ss {
 
-// Forward launch: one 256-thread block per 16x16-pixel tile and view.  Tiles
-// form FT_GH x FT_GW groups; groups go round-robin to the 8 XCDs (hardware
-// block h runs on XCD h % 8), and within a group the views are innermost.
-constexpr int FT_GH = 2, FT_GW = 2;
-__host__ __device__ inline int fwd_groups(int tR, int tC) {
-    return ((tR + FT_GH - 1) / FT_GH) * ((tC + FT_GW - 1) / FT_GW);
-}
-__host__ __device__ inline int64_t fwd_blocks(int tR, int tC, int V) {
-    return (int64_t)((fwd_groups(tR, tC) + 7) / 8 * 8) * FT_GH * FT_GW * V;
-}
-
 // Zero-padded copy of the coefficients for the forward walk: FWD_PAD(n)
 // zero layers on every side, so that the (n+1)^3 block of every knot cell of
 // the support-padded box (and of one cell beyond) is inside the copy.
@@ -62,19 +51,8 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
     constexpr double kap = (double)Degree<n>::kap;
     constexpr int qoff = CellBasis<n>::qoff;
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
-    // hardware block h runs on XCD h % 8: that XCD takes tile groups
-    // x, x + 8, x + 16, ... (spread over the detector, so the XCDs get equal
-    // work), each group for all views with the views innermost, so that the
-    // blocks it runs at one time walk neighbouring lines of consecutive
-    // views and share coefficient lines in its L2
-    const int per = FT_GH * FT_GW * V;
-    const int x = blockIdx.x % 8, l = blockIdx.x / 8;
-    const int G = (l / per) * 8 + x, inner = l % per;
-    const int v = inner % V, q = inner / V;
-    if (G >= fwd_groups(tR, tC)) return;  // padding group
-    const int gC = (tC + FT_GW - 1) / FT_GW;
-    const int tr = (G / gC) * FT_GH + q / FT_GW, tc = (G % gC) * FT_GW + q % FT_GW;
-    if (tr >= tR || tc >= tC) return;  // padding tile of an edge group
+    int v, tr, tc;
+    if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot
     const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);

@@ -332,12 +332,12 @@ __global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__rest
                                                           int C, const MlpImage *__restrict__ img,
                                                           float *__restrict__ y) {
     __shared__ MlpImage Wt;
+    const int tR = (R + 15) / 16, tC = (C + 15) / 16;
+    int v, tr, tc;
+    if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot: the whole block
     load_image(Wt, img);
     __syncthreads();
-    const int tR = (R + 15) / 16, tC = (C + 15) / 16;
-    const int nblocks = V * tR * tC;
-    const int b = xcd_remap(blockIdx.x, nblocks);
-    const int v = b / (tR * tC), rem = b % (tR * tC);
+    const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int i = (rem % tC) * 16 + (wave & 1) * 8 + (lane & 7);
@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(64) footprint_mlp_kernel(const float *__restri
 template <int n>
 static hipError_t launch_project_mlp_n(const LaunchArgs &a, hipStream_t st) {
     const int tR = (a.R + 15) / 16, tC = (a.C + 15) / 16;
-    hipLaunchKernelGGL(project_mlp_kernel<n>, dim3(a.V * tR * tC), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1],
+    hipLaunchKernelGGL(project_mlp_kernel<n>, dim3((unsigned)fwd_blocks(tR, tC, a.V)), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1],
                        a.N[2], a.geom, a.kind, a.V, a.R, a.C, (const MlpImage *)a.mlp, a.sino);
     return hipGetLastError();
 }

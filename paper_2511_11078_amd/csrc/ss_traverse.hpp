@@ -23,6 +23,34 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     return t;
 }
 
+// Forward launches: one 256-thread block per 16x16-pixel tile and view.
+// Tiles form FT_GH x FT_GW groups; the groups go round-robin to the 8 XCDs
+// (hardware block h runs on XCD h % 8), and within a group the views are
+// innermost.  An XCD thus takes groups x, x + 8, x + 16, ... spread over the
+// detector (the XCDs get equal work), and the blocks it runs at one time walk
+// neighbouring lines of consecutive views, which share coefficient lines in
+// its L2.
+constexpr int FT_GH = 2, FT_GW = 2;
+__host__ __device__ inline int fwd_groups(int tR, int tC) {
+    return ((tR + FT_GH - 1) / FT_GH) * ((tC + FT_GW - 1) / FT_GW);
+}
+__host__ __device__ inline int64_t fwd_blocks(int tR, int tC, int V) {
+    return (int64_t)((fwd_groups(tR, tC) + 7) / 8 * 8) * FT_GH * FT_GW * V;
+}
+// View and tile of this block; false for a padding slot (a whole block).
+__device__ __forceinline__ bool fwd_block_tile(int V, int tR, int tC, int &v, int &tr, int &tc) {
+    const int per = FT_GH * FT_GW * V;
+    const int x = blockIdx.x % 8, l = blockIdx.x / 8;
+    const int G = (l / per) * 8 + x, inner = l % per;
+    v = inner % V;
+    const int q = inner / V;
+    if (G >= fwd_groups(tR, tC)) return false;
+    const int gC = (tC + FT_GW - 1) / FT_GW;
+    tr = (G / gC) * FT_GH + q / FT_GW;
+    tc = (G % gC) * FT_GW + q % FT_GW;
+    return tr < tR && tc < tC;
+}
+
 struct ViewProj {    // detector coordinates of a world point (FP64 set-up)
     double d0[3], s[3], du_s[3], dv_s[3], nrm[3];
     double plane;    // (d0 - s) . nrm  (cone)
