@@ -26,7 +26,8 @@ struct ss_ctx {
     float *h_stage = nullptr;       // pinned staging for uploads
     hipEvent_t staged = nullptr;    // last upload read from h_stage
     bool staged_pending = false;
-    std::vector<float> last_vecs;   // host copy of what d_geom holds
+    std::vector<float> last_vecs;   // host copy of the view vectors d_geom holds
+    int last_kind = -1;             // and their geometry kind
     double *d_partials = nullptr;   // dot-product partial sums
     void *d_mlp = nullptr;          // network weights in kernel layout
     float *d_cells = nullptr;       // quadrature scratch: padded coefficients (forward), knot-cell table (adjoint)
@@ -129,13 +130,22 @@ ss_status check_geom(const ss_geometry *g) {
     return SS_OK;
 }
 
-// Upload the geometry if it differs from what the device buffer holds.
+// Float offset of the per-view projections behind the view vectors.
+size_t vproj_offset(size_t n_views) { return (n_views * 12 + 3) / 4 * 4; }
+
+// Upload the geometry if it differs from what the device buffer holds: the
+// view vectors, followed by each view's detector projection (FP64, computed
+// here once instead of by every block of the adjoint at every view).
 ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
-    const size_t nf = (size_t)g->n_views * 12;
-    if (ctx->last_vecs.size() == nf && std::memcmp(ctx->last_vecs.data(), g->vecs, nf * sizeof(float)) == 0)
+    const size_t nv = (size_t)g->n_views;
+    const size_t nf = nv * 12;
+    if (ctx->last_vecs.size() == nf && ctx->last_kind == (int)g->kind &&
+        std::memcmp(ctx->last_vecs.data(), g->vecs, nf * sizeof(float)) == 0)
         return SS_OK;
+    const size_t vp_off = vproj_offset(nv);
+    const size_t total = vp_off + nv * (sizeof(ss::ViewProj) / sizeof(float));
     hipError_t e;
-    if (nf > ctx->geom_cap) {
+    if (total > ctx->geom_cap) {
         // the old buffers may still be read by enqueued work: wait for it
         if (ctx->d_geom || ctx->h_stage) {
             if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -145,7 +155,7 @@ ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
             ctx->h_stage = nullptr;
             ctx->staged_pending = false;
         }
-        size_t cap = nf < 4096 ? 4096 : nf;
+        size_t cap = total < 4096 ? 4096 : total;
         if ((e = hipMalloc(&ctx->d_geom, cap * sizeof(float))) != hipSuccess) {
             ctx->geom_cap = 0;
             return fail(SS_ENOMEM, "geometry buffer: %s", hipGetErrorString(e));
@@ -163,11 +173,15 @@ ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
         ctx->staged_pending = false;
     }
     std::memcpy(ctx->h_stage, g->vecs, nf * sizeof(float));
-    if ((e = hipMemcpyAsync(ctx->d_geom, ctx->h_stage, nf * sizeof(float), hipMemcpyHostToDevice, st)) != hipSuccess)
+    ss::ViewProj *vp = reinterpret_cast<ss::ViewProj *>(ctx->h_stage + vp_off);
+    for (size_t v = 0; v < nv; ++v) ss::make_viewproj(g->vecs + 12 * v, (int)g->kind, vp[v]);
+    if ((e = hipMemcpyAsync(ctx->d_geom, ctx->h_stage, total * sizeof(float), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
         return hip_fail(e, "geometry upload");
     if ((e = hipEventRecord(ctx->staged, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ctx->staged_pending = true;
     ctx->last_vecs.assign(g->vecs, g->vecs + nf);
+    ctx->last_kind = (int)g->kind;
     return SS_OK;
 }
 
@@ -291,6 +305,7 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
     if (ss_status s = upload_geom(ctx, geom, st)) return s;
     ss::LaunchArgs a{};
     a.geom = ctx->d_geom;
+    a.vproj = reinterpret_cast<const ss::ViewProj *>(ctx->d_geom + vproj_offset((size_t)geom->n_views));
     a.N[0] = (int)dims[0];
     a.N[1] = (int)dims[1];
     a.N[2] = (int)dims[2];

@@ -347,7 +347,8 @@ __device__ __forceinline__ void shadow_rect(const float2 *corner, int sx, int sy
 
 template <int n>
 __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2,
-                                                                const float *__restrict__ geom, int kind, int V,
+                                                                const float *__restrict__ geom,
+                                                                const ViewProj *__restrict__ vps, int kind, int V,
                                                                 int R, int C, int mz0, int L,
                                                                 float *__restrict__ T) {
     using Rule = GLRule<Degree<n>::m>;
@@ -383,11 +384,7 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
 
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
-        if (tid == 0) {
-            ViewProj vp;
-            make_viewproj(e, kind, vp);
-            make_localproj(vp, centre, lp);
-        }
+        if (tid == 0) make_localproj(vps[v], centre, lp);
         __syncthreads();
         // detector position (pixel units) of every lattice corner of the brick
         for (int t = tid; t < NCORNER; t += blockDim.x) {
@@ -668,7 +665,7 @@ static hipError_t launch_backproject_n(const LaunchArgs &a, hipStream_t st) {
         const int L = std::min(Lmax, mlo + M2 - s);
         const int nb = ((M0 + GX - 1) / GX) * ((M1 + GY - 1) / GY) * ((L + GZ - 1) / GZ);
         hipLaunchKernelGGL(backproject_cells_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1],
-                           a.N[2], a.geom, a.kind, a.V, a.R, a.C, s, L, a.scratch);
+                           a.N[2], a.geom, a.vproj, a.kind, a.V, a.R, a.C, s, L, a.scratch);
         const int qz0 = s + qoff + n, qz1 = std::min(s + L - 1 + qoff, a.N[2] - 1);
         if (qz1 >= qz0) {
             const int64_t cnt = plane * (qz1 - qz0 + 1);

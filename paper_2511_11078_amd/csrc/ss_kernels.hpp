@@ -30,6 +30,7 @@ struct LaunchArgs {
     const float *sino_in;  // adjoint input
     float *coeffs_out;     // adjoint output
     const float *geom;     // device, V x 12
+    const ViewProj *vproj; // device, V detector projections (FP64)
     int N[3];
     int kind, V, R, C;
     const void *mlp;       // device weights (network form)

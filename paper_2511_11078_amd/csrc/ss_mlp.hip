@@ -432,7 +432,8 @@ __device__ __forceinline__ void fill_ray_m(RayRecM &rec, const float *__restrict
 
 template <int n>
 __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__restrict__ y, int N0, int N1, int N2,
-                                                              const float *__restrict__ geom, int kind, int V,
+                                                              const float *__restrict__ geom,
+                                                              const ViewProj *__restrict__ vps, int kind, int V,
                                                               int R, int C, const MlpImage *__restrict__ img,
                                                               float *__restrict__ c) {
     __shared__ MlpImage Wt;
@@ -459,7 +460,7 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
         const float *e = geom + 12 * v;
         __syncthreads();
         if (tid == 0) {
-            make_viewproj(e, kind, vp);
+            vp = vps[v];
             make_localproj(vp, centre, lp);
             double lo[3], hi[3];
 #pragma unroll
@@ -612,7 +613,7 @@ template <int n>
 static hipError_t launch_backproject_mlp_n(const LaunchArgs &a, hipStream_t st) {
     const int nb = ((a.N[0] + MBX - 1) / MBX) * ((a.N[1] + MBY - 1) / MBY) * ((a.N[2] + MBZ - 1) / MBZ);
     hipLaunchKernelGGL(backproject_mlp_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1], a.N[2],
-                       a.geom, a.kind, a.V, a.R, a.C, (const MlpImage *)a.mlp, a.coeffs_out);
+                       a.geom, a.vproj, a.kind, a.V, a.R, a.C, (const MlpImage *)a.mlp, a.coeffs_out);
     return hipGetLastError();
 }
 

@@ -82,7 +82,7 @@ __device__ __forceinline__ bool to_detector(const ViewProj &P, const double X[3]
 
 // Dual basis: du_s . du = 1, du_s . dv = 0, du_s . m = 0 (m = w or the
 // detector normal), likewise dv_s.
-__device__ __forceinline__ void make_viewproj(const float *__restrict__ e, int kind, ViewProj &P) {
+__host__ __device__ inline void make_viewproj(const float *__restrict__ e, int kind, ViewProj &P) {
     double du[3], dv[3], m[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
