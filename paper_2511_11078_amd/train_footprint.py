@@ -23,8 +23,9 @@ a tolerance.  This script follows those steps with these choices:
 
 Usage:  python -m paper_2511_11078_amd.train_footprint --degree 3 --out weights/mlp_n3.bin
 
-The shipped degree-3 weights used --steps 80000 --qat-steps 8000 --batch 32768
---lr 2e-3 --threads 6 --pool 2000000 (about 70 minutes on 6 host cores).
+The shipped degree-3 and degree-2 weights used --steps 80000 --qat-steps 8000
+--batch 32768 --lr 2e-3 --threads 6 --pool 2000000 (about 60-70 minutes each
+on 6 host cores).
 """
 from __future__ import annotations
 
