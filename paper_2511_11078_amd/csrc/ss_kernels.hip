@@ -312,29 +312,11 @@ __device__ __forceinline__ void integrate_hit(const CellRay &r, const float lo[3
     }
 }
 
-// Pixels whose centre lies in the bounding rectangle of the projected
-// corners of the lattice box [x0, x0 + sx] x [y0, y0 + sy] x [z0, z0 + sz]
-// (corner table of the brick, pixel units).  The projection of the box is
-// the convex hull of its corners' projections, so every pixel whose line
-// meets the box is in the rectangle; PIX_MARGIN absorbs FP32 rounding.  If a
-// corner has no projection (on or behind the source plane), the whole
-// detector.
-__device__ __forceinline__ void shadow_rect(const float2 *corner, int sx, int sy, int sz, int x0, int y0, int z0,
-                                            int R, int C, int &i0, int &i1, int &j0, int &j1) {
-    float cmin = 3.0e38f, cmax = -3.0e38f, rmin = 3.0e38f, rmax = -3.0e38f;
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int cx = x0 + ((k & 1) ? sx : 0), cy = y0 + ((k & 2) ? sy : 0), cz = z0 + ((k & 4) ? sz : 0);
-        const float2 p = corner[(cz * (GY + 1) + cy) * (GX + 1) + cx];
-        bad = bad || p.x != p.x || p.y != p.y;
-        cmin = fminf(cmin, p.x); cmax = fmaxf(cmax, p.x);
-        rmin = fminf(rmin, p.y); rmax = fmaxf(rmax, p.y);
-    }
-    if (bad) {
-        i0 = 0; i1 = C - 1; j0 = 0; j1 = R - 1;
-        return;
-    }
+// Pixels whose centre lies in the continuous detector rectangle
+// [cmin, cmax] x [rmin, rmax] (pixel units), clamped to the detector;
+// PIX_MARGIN absorbs the FP32 rounding of the corner table.
+__device__ __forceinline__ void pixel_rect(float cmin, float cmax, float rmin, float rmax, int R, int C, int &i0,
+                                           int &i1, int &j0, int &j1) {
     // clamped in FP32 before converting
     const float fi0 = fmaxf(ceilf(cmin - PIX_MARGIN), 0.0f), fi1 = fminf(floorf(cmax + PIX_MARGIN), (float)(C - 1));
     const float fj0 = fmaxf(ceilf(rmin - PIX_MARGIN), 0.0f), fj1 = fminf(floorf(rmax + PIX_MARGIN), (float)(R - 1));
@@ -342,6 +324,22 @@ __device__ __forceinline__ void shadow_rect(const float2 *corner, int sx, int sy
         i0 = (int)fi0; i1 = (int)fi1; j0 = (int)fj0; j1 = (int)fj1;
     } else {
         i0 = 0; i1 = -1; j0 = 0; j1 = -1;
+    }
+}
+
+// Bounding rectangle of the projected corners of the lattice box
+// [x0, x0 + sx] x [y0, y0 + sy] x [z0, z0 + sz] (corner table of the brick).
+// The projection of the box is the convex hull of its corners' projections,
+// so every pixel whose line meets the box is in the rectangle.
+__device__ __forceinline__ void corner_bounds(const float2 *corner, int sx, int sy, int sz, int x0, int y0, int z0,
+                                              float &cmin, float &cmax, float &rmin, float &rmax) {
+    cmin = 3.0e38f; cmax = -3.0e38f; rmin = 3.0e38f; rmax = -3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int cx = x0 + ((k & 1) ? sx : 0), cy = y0 + ((k & 2) ? sy : 0), cz = z0 + ((k & 4) ? sz : 0);
+        const float2 p = corner[(cz * (GY + 1) + cy) * (GX + 1) + cx];
+        cmin = fminf(cmin, p.x); cmax = fmaxf(cmax, p.x);
+        rmin = fminf(rmin, p.y); rmax = fmaxf(rmax, p.y);
     }
 }
 
@@ -387,20 +385,33 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
         if (tid == 0) make_localproj(vps[v], centre, lp);
         __syncthreads();
         // detector position (pixel units) of every lattice corner of the brick
+        bool bad = false;  // a corner on or behind the source plane: no bounded shadow
         for (int t = tid; t < NCORNER; t += blockDim.x) {
             const int cx = t % (GX + 1), cy = (t / (GX + 1)) % (GY + 1), cz = t / ((GX + 1) * (GY + 1));
             const float d[3] = {(float)cx - 0.5f * GX, (float)cy - 0.5f * GY, (float)cz - 0.5f * GZ};
-            float cc, rr;
-            corner[t] = local_to_detector(lp, d, cc, rr) ? make_float2(cc + oc, rr + orow)
-                                                         : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            float cc = 0.0f, rr = 0.0f;
+            const bool ok = local_to_detector(lp, d, cc, rr);
+            bad = bad || !ok;
+            corner[t] = make_float2(cc + oc, rr + orow);
         }
-        __syncthreads();
+        const bool anybad = __syncthreads_or(bad);
         // the brick's pixel rectangle (from its eight corners, the same for
         // every thread) and this cell's candidate pixels (from its own)
         int bi0, bi1, bj0, bj1;
-        shadow_rect(corner, GX, GY, GZ, 0, 0, 0, R, C, bi0, bi1, bj0, bj1);
         int mi0 = 0, mi1 = -1, mj0 = 0, mj1 = -1;
-        if (mine) shadow_rect(corner, 1, 1, 1, tx, ty, tz, R, C, mi0, mi1, mj0, mj1);
+        if (anybad) {
+            bi0 = 0; bi1 = C - 1; bj0 = 0; bj1 = R - 1;
+            if (mine) { mi0 = 0; mi1 = C - 1; mj0 = 0; mj1 = R - 1; }
+        } else {
+            float bc0, bc1, br0, br1;
+            corner_bounds(corner, GX, GY, GZ, 0, 0, 0, bc0, bc1, br0, br1);
+            pixel_rect(bc0, bc1, br0, br1, R, C, bi0, bi1, bj0, bj1);
+            if (mine) {
+                float c0, c1, r0, r1;
+                corner_bounds(corner, 1, 1, 1, tx, ty, tz, c0, c1, r0, r1);
+                pixel_rect(c0, c1, r0, r1, R, C, mi0, mi1, mj0, mj1);
+            }
+        }
         // the view's lines go into the table in segments of whole rows (of
         // columns, for a row wider than the table); this cell's hits are
         // queued and integrated when the table or the batch of views is full
