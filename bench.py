@@ -56,14 +56,16 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "74e39fa9ddc5f4f4f352fa9bb60834f8fc3c319c08b165e13e416cdf7cacc4c5"
+TRAFFIC_SHA256 = "875065ae3fc843d752e65fb3f422c052fcb98c6dbaaeb3086afbb64c6c5be19a"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("project_kernel", 3): (2.0 * 1263418 * 1024, 1.0 * 238736 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 2986507 * 1024, 1.0 * 5732001 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2475118 * 1024, 1.0 * 65536 * 1024),
-    ("project_kernel", 0): (2.0 * 970820 * 1024, 1.0 * 246110 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1216239 * 1024, 1.0 * 67048 * 1024),
-    ("cells_to_coeffs_kernel", 0): (2.0 * 32790 * 1024, 1.0 * 65536 * 1024),
+    ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
+    ("project_kernel", 3): (2.0 * 1519505 * 1024, 1.0 * 236752 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3042567 * 1024, 1.0 * 5839532 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2476640 * 1024, 1.0 * 65536 * 1024),
+    ("pad_volume_kernel", 0): (2.0 * 36896 * 1024, 1.0 * 67084 * 1024),
+    ("project_kernel", 0): (2.0 * 1070289 * 1024, 1.0 * 254422 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1225181 * 1024, 1.0 * 66962 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32784 * 1024, 1.0 * 65536 * 1024),
 }
 
 
@@ -234,7 +236,7 @@ def main():
             fl_f = R * cells_per_ray * cell_flops(n)
             # adjoint: the same (line, cell) units, then (n+1)^3 adds per coefficient
             fl_a = R * cells_per_ray * cell_flops(n) + 2.0 * nb3 * float(np.prod(dims))
-            for name, ms, fl, unit in ((f"project_kernel<{n}> (knot-cell walk)", r0["fwd_ms"], fl_f,
+            for name, ms, fl, unit in ((f"pad_volume_kernel + project_kernel<{n}> (knot-cell walk)", r0["fwd_ms"], fl_f,
                                         f"{cell_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} cells/line"),
                                        (f"backproject_cells_kernel<{n}> + cells_to_coeffs_kernel<{n}> "
                                         f"(knot-cell gather)", r0["adj_ms"], fl_a,
