@@ -85,17 +85,43 @@ def measured_traffic(kernels, degree: int, workload: str):
     return float(sum(sum(TRAFFIC_BYTES[(k, degree)]) for k in kernels))
 
 
-def cell_flops(n: int) -> float:
-    """Algorithmic FP32 work of one (line, knot cell) unit: at each of the m
-    Gauss-Legendre nodes, the n+1 blending weights of three axes (2n + 3
-    operations each), the contraction of the (n+1)^3 block with the three
-    weight vectors ((n+1)^3 + (n+1)^2 + (n+1) FMA: the forward contracts the
-    coefficient block, the adjoint accumulates the outer product, the same
-    count) and 4 operations for the node map and the weighted sum; 2 flops
-    per operation."""
-    m = GL_ORDER[n]
+# FP32 flops of the blending weights of one axis at one node (cell_weights):
+# FMA = 2 flops, add or multiply = 1
+BLEND_FLOPS = {0: 0, 1: 1, 2: 7, 3: 15}
+
+
+def fwd_unit_flops(n: int) -> float:
+    """Algorithmic FP32 work of one (line, knot cell) unit of the forward: at
+    each of the m Gauss-Legendre nodes, the node map (3 FMA), the n+1 blending
+    weights of three axes, the contraction of the (n+1)^3 coefficient block
+    ((n+1)^3 + (n+1)^2 + (n+1) FMA) and the weighted sum (1 FMA), plus the
+    cell's accumulation (1 FMA).  Degree 0: coefficient times chord (1 FMA)."""
+    if n == 0:
+        return 2.0
+    nb, m = n + 1, GL_ORDER[n]
+    return m * (6 + 3 * BLEND_FLOPS[n] + 2 * (nb ** 3 + nb ** 2 + nb) + 2) + 2
+
+
+def adj_unit_flops(n: int) -> float:
+    """Algorithmic FP32 work of one (line, knot cell) unit of the adjoint, which
+    accumulates centred moments: the chord through the cell (about 32 flops:
+    slab test, midpoint, half-length, centred start and step) and at each node
+    the node map (3 FMA), the powers of the three coordinates ((n+1) + 2(n-1)
+    multiplies, the first carrying the quadrature weight), the products of two
+    axes (n(n+1) multiplies) and the accumulation ((n+1)^2 adds and n(n+1)^2
+    FMA).  Degree 0: sinogram value times chord (1 FMA)."""
+    if n == 0:
+        return 2.0
+    nb, m = n + 1, GL_ORDER[n]
+    node = 6 + (nb + 2 * (n - 1)) + n * nb + nb * nb + 2 * n * nb * nb
+    return m * node + 32
+
+
+def adj_cell_flops(n: int) -> float:
+    """Once per knot cell and application: the blending map from moments to
+    per-basis integrals, one (n+1) x (n+1) matrix per axis on (n+1)^3 values."""
     nb = n + 1
-    return 2.0 * m * (3 * (2 * n + 3) + nb ** 3 + nb ** 2 + nb + 4)
+    return 0.0 if n == 0 else 3.0 * 2 * nb ** 4
 
 
 def main():
@@ -233,15 +259,15 @@ def main():
         kernels = []
         if main_form == "quad":
             nb3 = (n + 1) ** 3
-            fl_f = R * cells_per_ray * cell_flops(n)
-            # adjoint: the same (line, cell) units, then (n+1)^3 adds per coefficient
-            fl_a = R * cells_per_ray * cell_flops(n) + 2.0 * nb3 * float(np.prod(dims))
+            ncells = float(np.prod([d + n for d in dims]))
+            fl_f = R * cells_per_ray * fwd_unit_flops(n)
+            fl_a = R * cells_per_ray * adj_unit_flops(n) + ncells * adj_cell_flops(n) + nb3 * float(np.prod(dims))
             for name, ms, fl, unit in ((f"pad_volume_kernel + project_kernel<{n}> (knot-cell walk)", r0["fwd_ms"], fl_f,
-                                        f"{cell_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} cells/line"),
+                                        f"{fwd_unit_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} cells/line"),
                                        (f"backproject_cells_kernel<{n}> + cells_to_coeffs_kernel<{n}> "
                                         f"(knot-cell gather)", r0["adj_ms"], fl_a,
-                                        f"{cell_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} "
-                                        f"cells/line + {2 * nb3} flop per coefficient")):
+                                        f"{adj_unit_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} "
+                                        f"cells/line + {adj_cell_flops(n):.0f} per cell + {nb3} per coefficient")):
                 ach = fl / (ms / 1e3) / 1e12
                 knames = [part.strip().split("<")[0] for part in name.split(" (")[0].split("+")]
                 kernels.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
