@@ -1,12 +1,14 @@
 // ss_kernels.hip -- gfx950 kernels of the spline x-ray transform.
 //
-//   project_kernel      forward model, one line per lane (quadrature form)
+//   pad_volume_kernel + project_kernel
+//                       forward model, one line per lane (quadrature form)
 //   backproject_cells_kernel + cells_to_coeffs_kernel
 //                       transpose: knot-cell gather, then coefficient gather (atomic-free)
 //   footprint_kernel    P phi(w, x) for arbitrary pairs (diagnostics)
 //   dot / axpy / xpay / ratio kernels for the least-squares loop
 //
-// The network form lives in ss_mlp.hip and reuses the traversal below.
+// The network form lives in ss_mlp.hip and shares the line set-up, block
+// order and detector mapping of ss_math.hpp and ss_traverse.hpp.
 #include "ss_kernels.hpp"
 
 #include <algorithm>
@@ -53,10 +55,9 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
     int v, tr, tc;
     if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot
-    const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const int i = (rem % tC) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int j = tr * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int i = tc * 16 + (wave & 1) * 8 + (lane & 7);
     if (v >= V || j >= R || i >= C) return;
     const int N[3] = {N0, N1, N2};
     const double centre[3] = {0.0, 0.0, 0.0};
@@ -188,7 +189,8 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // restriction of basis q to the line, for each of the (n+1)^3 bases q whose
 // support covers K.  Pass 1 gives every knot cell to one thread, which
 // gathers, over all views, the lines of the pixels whose centres fall in the
-// detector shadow of its cell and accumulates the (n+1)^3 per-basis
+// detector shadow of its cell, accumulates the centred moments of their
+// chords (integrate_hit) and at the end maps them to the (n+1)^3 per-basis
 // integrals (T[K][a] below, a = q - K - qoff per axis).  Pass 2 gives every
 // coefficient to one thread, which adds its (n+1)^3 entries T[q - qoff - a][a]
 // of the cells its support covers.  Every (line, basis) pair of eq. (4)

@@ -337,10 +337,9 @@ __global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__rest
     if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot: the whole block
     load_image(Wt, img);
     __syncthreads();
-    const int rem = tr * tC + tc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = (rem / tC) * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const int i = (rem % tC) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int j = tr * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int i = tc * 16 + (wave & 1) * 8 + (lane & 7);
     const bool pix = v < V && j < R && i < C;
     const int N[3] = {N0, N1, N2};
     const double centre[3] = {0.0, 0.0, 0.0};
