@@ -204,11 +204,12 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // appends the lines of the brick's pixel rectangle to an LDS table (FP64
 // set-up, anchor re-based at the brick centre), and every thread takes the
 // bounding rectangle of its own cell's eight projected corners as its
-// candidate pixels.  A thread queues the candidates whose chord through its
-// cell is non-empty and integrates its queue once the table holds
-// VIEWS_PER_BATCH views (or is full): the wave then runs as many integration
-// rounds as its busiest lane has hits over the whole batch, not over each
-// view, and never spends a round on a candidate that misses.
+// candidate pixels (about 95 % of them hit the cell).  A thread queues its
+// candidates without reading their lines and integrates its queue once the
+// table holds VIEWS_PER_BATCH views (or is full), dropping the few whose
+// chord through the cell is empty: the wave then runs as many integration
+// rounds as its busiest lane has candidates over the whole batch, not over
+// each view.
 //
 // The cell table T holds (n+1)^3 FP32 entries per cell, entry-major
 // (T[a * cells + K], K x-fastest over the cells of a z-chunk), so that both
@@ -220,7 +221,7 @@ constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
 constexpr int CRAY_CAP = 832;                   // lines in the LDS table
 constexpr int VIEWS_PER_BATCH = 8;              // views whose hits are integrated together
-constexpr int HITQ_CAP = 32;                    // queued hits per thread
+constexpr int HITQ_CAP = 32;                    // queued candidates per thread
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
 struct __attribute__((aligned(8))) CellRay {  // 40 bytes
@@ -274,7 +275,7 @@ __device__ __forceinline__ void integrate_hit(const CellRay &r, const float lo[3
     using Rule = GLRule<Degree<n>::m>;
     constexpr int NB = n + 1;
     float t0, t1;
-    cell_chord<n>(r, lo, t0, t1);
+    if (!cell_chord<n>(r, lo, t0, t1)) return;  // a candidate whose line misses the cell
     const float mid = 0.5f * (t0 + t1), half = 0.5f * (t1 - t0);
     float uc[3], du[3];  // centred cell coordinate at mid, and its step
 #pragma unroll
@@ -356,7 +357,7 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
     __shared__ CellRay rays[CRAY_CAP];
-    __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of table indices
+    __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of candidate table indices
     __shared__ float2 corner[NCORNER];
     __shared__ LocalProj lp;
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
@@ -444,17 +445,12 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
                     const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
                     for (int jj = j0; jj <= j1; ++jj)
                         for (int ii = i0; ii <= i1; ++ii) {
-                            const int idx = used + (jj - cj0) * cw + (ii - ci0);
-                            float t0, t1;
-                            if (cell_chord<n>(rays[idx], lo, t0, t1)) {
-                                if (nhit == HITQ_CAP) {  // queue full: integrate it now
-                                    for (int k = 0; k < nhit; ++k)
-                                        integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
-                                    nhit = 0;
-                                }
-                                hitq[nhit * 256 + tid] = (unsigned short)idx;
-                                ++nhit;
+                            if (nhit == HITQ_CAP) {  // queue full: integrate it now
+                                for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
+                                nhit = 0;
                             }
+                            hitq[nhit * 256 + tid] = (unsigned short)(used + (jj - cj0) * cw + (ii - ci0));
+                            ++nhit;
                         }
                     used += cn;
                 }
