@@ -346,12 +346,13 @@ __device__ __forceinline__ void corner_bounds(const float2 *corner, int sx, int 
     }
 }
 
+// Three waves per SIMD (at most 168 VGPRs) keep three blocks on a CU to hide
+// the per-view set-up between barriers.
 template <int n>
-__global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2,
-                                                                const float *__restrict__ geom,
-                                                                const ViewProj *__restrict__ vps, int kind, int V,
-                                                                int R, int C, int mz0, int L,
-                                                                float *__restrict__ T) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, const float *__restrict__ geom,
+                         const ViewProj *__restrict__ vps, int kind, int V, int R, int C, int mz0, int L,
+                         float *__restrict__ T) {
     using Rule = GLRule<Degree<n>::m>;
     constexpr int NB = n + 1;
     constexpr int qoff = CellBasis<n>::qoff;
@@ -359,7 +360,6 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     __shared__ CellRay rays[CRAY_CAP];
     __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of candidate table indices
     __shared__ float2 corner[NCORNER];
-    __shared__ LocalProj lp;
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
     const int nbx = (M0 + GX - 1) / GX, nby = (M1 + GY - 1) / GY, nbz = (L + GZ - 1) / GZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -382,20 +382,29 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
     for (int e = 0; e < NB * NB * NB; ++e) acc[e] = 0.0f;
     int used = 0, nviews = 0;  // table entries and views of the current batch (block-uniform)
     int nhit = 0;              // this thread's queued hits
+    bool synced = true;        // block-uniform: every thread is past its reads of the corner table
 
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
-        if (tid == 0) make_localproj(vps[v], centre, lp);
-        __syncthreads();
+        LocalProj lp;  // the same in every thread
+        make_localproj(vps[v], centre, lp);
+        // the previous view's corner table may still be read unless a
+        // segment barrier has passed since
+        if (!synced) __syncthreads();
+        synced = false;
         // detector position (pixel units) of every lattice corner of the brick
         bool bad = false;  // a corner on or behind the source plane: no bounded shadow
-        for (int t = tid; t < NCORNER; t += blockDim.x) {
-            const int cx = t % (GX + 1), cy = (t / (GX + 1)) % (GY + 1), cz = t / ((GX + 1) * (GY + 1));
-            const float d[3] = {(float)cx - 0.5f * GX, (float)cy - 0.5f * GY, (float)cz - 0.5f * GZ};
-            float cc = 0.0f, rr = 0.0f;
-            const bool ok = local_to_detector(lp, d, cc, rr);
-            bad = bad || !ok;
-            corner[t] = make_float2(cc + oc, rr + orow);
+#pragma unroll
+        for (int it = 0; it < (NCORNER + 255) / 256; ++it) {  // independent iterations
+            const int t = tid + 256 * it;
+            if (t < NCORNER) {
+                const int cx = t % (GX + 1), cy = (t / (GX + 1)) % (GY + 1), cz = t / ((GX + 1) * (GY + 1));
+                const float d[3] = {(float)cx - 0.5f * GX, (float)cy - 0.5f * GY, (float)cz - 0.5f * GZ};
+                float cc = 0.0f, rr = 0.0f;
+                const bool ok = local_to_detector(lp, d, cc, rr);
+                bad = bad || !ok;
+                corner[t] = make_float2(cc + oc, rr + orow);
+            }
         }
         const bool anybad = __syncthreads_or(bad);
         // the brick's pixel rectangle (from its eight corners, the same for
@@ -433,14 +442,16 @@ __global__ void __launch_bounds__(256) backproject_cells_kernel(const float *__r
                         nhit = 0;
                         used = 0;
                         nviews = 0;
+                        __syncthreads();  // the table is refilled from its start
                     }
-                    __syncthreads();
+                    // new entries go past every queued one: no barrier needed
                     for (int t = tid; t < cn; t += blockDim.x) {
                         const int jj = cj0 + t / cw, ii = ci0 + t % cw;
                         fill_cellray(rays[used + t], e, kind, R, C, jj, ii, centre,
                                      y[((int64_t)v * R + jj) * C + ii]);
                     }
                     __syncthreads();
+                    synced = true;
                     const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
                     const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
                     for (int jj = j0; jj <= j1; ++jj)

@@ -311,7 +311,16 @@ __device__ __forceinline__ LineD make_line(const float *__restrict__ e, int kind
     }
     const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     L.ok = nn > 0.0;
-    const double inv = L.ok ? 1.0 / sqrt(nn) : 0.0;
+    // 1/|d|: the FP32 reciprocal square root refined by one Newton step in
+    // FP64 (relative error ~1e-14, a short dependency chain), exact division
+    // outside the FP32 range
+    double inv;
+    if (nn > 1.0e-30 && nn < 1.0e30) {
+        const double r0 = (double)__builtin_amdgcn_rsqf((float)nn);
+        inv = r0 * fma(-0.5 * nn, r0 * r0, 1.5);
+    } else {
+        inv = L.ok ? 1.0 / sqrt(nn) : 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) L.w[k] = d[k] * inv;
     double rel[3];
