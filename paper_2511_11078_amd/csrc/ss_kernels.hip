@@ -205,11 +205,13 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // set-up, anchor re-based at the brick centre), and every thread takes the
 // bounding rectangle of its own cell's eight projected corners as its
 // candidate pixels (about 95 % of them hit the cell).  A thread queues its
-// candidates without reading their lines and integrates its queue once the
-// table holds VIEWS_PER_BATCH views (or is full), dropping the few whose
-// chord through the cell is empty: the wave then runs as many integration
-// rounds as its busiest lane has candidates over the whole batch, not over
-// each view.
+// candidates without reading their lines in a ring, oldest first, and the
+// integration drops the few whose chord through the cell is empty.  The
+// table has two halves filled in turn (up to VIEWS_PER_HALF views each):
+// before a half is refilled, each wave runs as many integration rounds as
+// its lane with the most entries in that half needs, and lanes with fewer
+// take entries of the other half in the same rounds, so that the lanes of a
+// wave, whose candidate counts differ view by view, stay busy.
 //
 // The cell table T holds (n+1)^3 FP32 entries per cell, entry-major
 // (T[a * cells + K], K x-fastest over the cells of a z-chunk), so that both
@@ -219,9 +221,10 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // ---------------------------------------------------------------------------
 constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
-constexpr int CRAY_CAP = 832;                   // lines in the LDS table
-constexpr int VIEWS_PER_BATCH = 8;              // views whose hits are integrated together
-constexpr int HITQ_CAP = 32;                    // queued candidates per thread
+constexpr int CRAY_CAP = 832;                   // lines in the LDS table (two halves)
+constexpr int CRAY_HALF = CRAY_CAP / 2;
+constexpr int VIEWS_PER_HALF = 5;               // views whose lines fill one half
+constexpr int HITQ_CAP = 32;                    // queued candidates per thread (a ring)
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
 struct __attribute__((aligned(8))) CellRay {  // 40 bytes
@@ -380,8 +383,15 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     float acc[NB * NB * NB];
 #pragma unroll
     for (int e = 0; e < NB * NB * NB; ++e) acc[e] = 0.0f;
-    int used = 0, nviews = 0;  // table entries and views of the current batch (block-uniform)
-    int nhit = 0;              // this thread's queued hits
+    // block-uniform: the half being filled, its entries and views, and
+    // whether the other half has been filled before
+    int half = 0, used = 0, nviews = 0;
+    bool other_filled = false;
+    // this thread's queue: a ring of table indices, oldest first, in slots
+    // qhead + 256 k (mod the ring); the first `nolder` entries belong to the
+    // other half
+    constexpr int QMASK = HITQ_CAP * 256 - 1;
+    int qhead = tid, count = 0, nolder = 0;
     bool synced = true;        // block-uniform: every thread is past its reads of the corner table
 
     for (int v = 0; v < V; ++v) {
@@ -429,25 +439,43 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
         // queued and integrated when the table or the batch of views is full
         const int W = bi1 - bi0 + 1;
         if (W > 0 && bj1 >= bj0) {
-            const int rows_per_seg = max(1, CRAY_CAP / W);
-            const int cols = min(W, CRAY_CAP);
+            const int rows_per_seg = max(1, CRAY_HALF / W);
+            const int cols = min(W, CRAY_HALF);
             for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_seg) {
                 const int cj1 = min(bj1, cj0 + rows_per_seg - 1);
                 for (int ci0 = bi0; ci0 <= bi1; ci0 += cols) {
                     const int ci1 = min(bi1, ci0 + cols - 1);
                     const int cw = ci1 - ci0 + 1;
                     const int cn = (cj1 - cj0 + 1) * cw;
-                    if (used + cn > CRAY_CAP || nviews == VIEWS_PER_BATCH) {
-                        for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
-                        nhit = 0;
+                    if (used + cn > CRAY_HALF || nviews == VIEWS_PER_HALF) {
+                        // switch halves.  Before the other half is refilled,
+                        // every lane retires its entries there; lanes with
+                        // fewer of them integrate entries of this half in the
+                        // same rounds (the wave runs as many rounds as its
+                        // lane with the most entries in the other half)
+                        if (other_filled) {
+                            int K = nolder;
+#pragma unroll
+                            for (int m = 32; m >= 1; m >>= 1) K = max(K, __shfl_xor(K, m));
+                            const int npop = min(K, count);
+                            for (int k = 0; k < npop; ++k) {
+                                integrate_hit<n>(rays[hitq[qhead]], lo, acc);
+                                qhead = (qhead + 256) & QMASK;
+                            }
+                            count -= npop;
+                            __syncthreads();  // no wave reads the other half any more
+                        }
+                        nolder = count;  // every queued entry is now in the older half
+                        half ^= 1;
                         used = 0;
                         nviews = 0;
-                        __syncthreads();  // the table is refilled from its start
+                        other_filled = true;
                     }
                     // new entries go past every queued one: no barrier needed
+                    const int tb = half * CRAY_HALF + used;  // first table entry of the segment
                     for (int t = tid; t < cn; t += blockDim.x) {
                         const int jj = cj0 + t / cw, ii = ci0 + t % cw;
-                        fill_cellray(rays[used + t], e, kind, R, C, jj, ii, centre,
+                        fill_cellray(rays[tb + t], e, kind, R, C, jj, ii, centre,
                                      y[((int64_t)v * R + jj) * C + ii]);
                     }
                     __syncthreads();
@@ -456,12 +484,14 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                     const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
                     for (int jj = j0; jj <= j1; ++jj)
                         for (int ii = i0; ii <= i1; ++ii) {
-                            if (nhit == HITQ_CAP) {  // queue full: integrate it now
-                                for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
-                                nhit = 0;
+                            if (count == HITQ_CAP) {  // queue full: integrate its oldest entry now
+                                integrate_hit<n>(rays[hitq[qhead]], lo, acc);
+                                qhead = (qhead + 256) & QMASK;
+                                --count;
+                                nolder = max(nolder - 1, 0);
                             }
-                            hitq[nhit * 256 + tid] = (unsigned short)(used + (jj - cj0) * cw + (ii - ci0));
-                            ++nhit;
+                            hitq[(qhead + 256 * count) & QMASK] = (unsigned short)(tb + (jj - cj0) * cw + (ii - ci0));
+                            ++count;
                         }
                     used += cn;
                 }
@@ -469,7 +499,10 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
             ++nviews;
         }
     }
-    for (int k = 0; k < nhit; ++k) integrate_hit<n>(rays[hitq[k * 256 + tid]], lo, acc);
+    for (int k = 0; k < count; ++k) {
+        integrate_hit<n>(rays[hitq[qhead]], lo, acc);
+        qhead = (qhead + 256) & QMASK;
+    }
     // moments -> per-basis integrals: apply the blending map along each axis
     if constexpr (n > 0) {
 #pragma unroll
