@@ -6,8 +6,9 @@ oracle for projections and back-projections; single footprints within
 2e-6 of the largest footprint value.  Edge cases: every degree, anisotropic
 volumes, detectors that are not a multiple of the 16 x 16 tile, lines that
 graze the volume or miss it, axis-aligned lines (zero slopes), diagonal
-lines through lattice edges (dominant-axis ties), a 1 x 1 x 1 volume,
-determinism and independence of how views are batched.
+lines through lattice edges (dominant-axis ties), a 1 x 1 x 1 volume, a
+cone source inside the volume, determinism and independence of how views
+are batched.
 """
 import numpy as np
 import pytest
@@ -173,6 +174,29 @@ def test_backproject_large_shadows(ctxs, case):
     e = rel_l2(got, want)
     say(f"  rel-L2 {e:.3e} over {coefs.size} coefficients")
     assert np.abs(want).max() > 0 and e <= TOL
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_source_inside_volume(ctxs, n):
+    """Cone source inside the volume (the whole line is integrated, so cells
+    behind the source are hit too).  Bricks with a corner on or behind the
+    source plane take every pixel of the detector as candidates: several
+    table segments per view, a switch of table halves within a view and a
+    per-thread queue that overflows and wraps many times."""
+    say(f"source inside the volume n={n}")
+    rng = np.random.default_rng(260 + n)
+    dims = (13, 11, 9)
+    geom = synth.cone_circular_geometry(3, 24, 26, src_radius=3.0, src_det=12.0, angle0=0.4)
+    c = rng.standard_normal(dims[::-1]).astype(np.float32)
+    got = to_np(ctxs[n].project(to_gpu(c), geom))
+    want = oracle.project(c, geom, n)
+    e = rel_l2(got, want)
+    y = rng.standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32)
+    gb = to_np(ctxs[n].backproject(to_gpu(y), geom, dims))
+    wb = oracle.backproject_subset(y, geom, dims, n)
+    eb = rel_l2(gb, wb)
+    say(f"  forward rel-L2 {e:.3e}, adjoint rel-L2 {eb:.3e}")
+    assert e <= TOL and eb <= TOL
 
 
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
