@@ -93,7 +93,7 @@ def test_network_gate_is_exact(mctx):
     assert np.count_nonzero(got[inside]) > 0.95 * inside.sum()
 
 
-@pytest.mark.parametrize("kind", ["parallel", "cone"])
+@pytest.mark.parametrize("kind", ["parallel", "cone", "cone_source_inside"])
 def test_network_projection_matches_pair_enumeration(mctx, blob, kind):
     say(f"network projection vs pair enumeration {kind}")
     dims = (11, 9, 7)
@@ -101,8 +101,10 @@ def test_network_projection_matches_pair_enumeration(mctx, blob, kind):
     c = rng.uniform(0.0, 1.0, dims[::-1]).astype(np.float32)
     if kind == "parallel":
         geom = tilted_parallel(3, 13, 15, seed=311)
-    else:
+    elif kind == "cone":
         geom = synth.cone_circular_geometry(3, 14, 13, src_radius=30.0, src_det=45.0, angle0=0.25)
+    else:  # lines through a source inside the volume (whole lines)
+        geom = synth.cone_circular_geometry(3, 14, 13, src_radius=2.5, src_det=10.0, angle0=0.25)
     got = to_np(mctx.project(to_gpu(c), geom)).ravel()
     want = _pairs_reference(blob, 3, c, geom)
     e = rel_l2(got, want)
@@ -110,15 +112,17 @@ def test_network_projection_matches_pair_enumeration(mctx, blob, kind):
     assert e <= 2e-4
 
 
-@pytest.mark.parametrize("kind", ["parallel", "cone"])
+@pytest.mark.parametrize("kind", ["parallel", "cone", "cone_source_inside"])
 def test_network_dot_product_test(mctx, kind):
     say(f"network dot test {kind}")
     dims = (30, 27, 25)
     rng = np.random.default_rng(320)
     if kind == "parallel":
         geom = tilted_parallel(5, 41, 37, seed=321)
-    else:
+    elif kind == "cone":
         geom = synth.cone_circular_geometry(5, 39, 43, src_radius=75.0, src_det=110.0, angle0=0.3)
+    else:  # coefficient boxes across the source plane take the whole detector
+        geom = synth.cone_circular_geometry(3, 24, 26, src_radius=4.0, src_det=16.0, angle0=0.3)
     x = to_gpu(rng.standard_normal(dims[::-1]).astype(np.float32))
     y = to_gpu(rng.standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32))
     Ax = mctx.project(x, geom)
