@@ -303,18 +303,17 @@ __device__ __forceinline__ void integrate_hit(const CellRay &r, const float lo[3
             P3[p] = p == 1 ? u3 : P3[p - 1] * u3;
         }
 #pragma unroll
-        for (int p2 = 0; p2 < NB; ++p2) {
-            float xy[NB];
+        for (int p3 = 0; p3 < NB; ++p3)
 #pragma unroll
-            for (int p1 = 0; p1 < NB; ++p1) xy[p1] = p2 == 0 ? P1[p1] : P2[p2] * P1[p1];
+            for (int p2 = 0; p2 < NB; ++p2) {
+                // z = u2^p2 u3^p3 (no product where either power is zero)
+                const float z = p3 == 0 ? P2[p2] : (p2 == 0 ? P3[p3] : P3[p3] * P2[p2]);
 #pragma unroll
-            for (int p1 = 0; p1 < NB; ++p1) acc[p2 * NB + p1] += xy[p1];
-#pragma unroll
-            for (int p3 = 1; p3 < NB; ++p3)
-#pragma unroll
-                for (int p1 = 0; p1 < NB; ++p1)
-                    acc[(p3 * NB + p2) * NB + p1] = fmaf(P3[p3], xy[p1], acc[(p3 * NB + p2) * NB + p1]);
-        }
+                for (int p1 = 0; p1 < NB; ++p1) {
+                    float &a = acc[(p3 * NB + p2) * NB + p1];
+                    a = (p2 == 0 && p3 == 0) ? a + P1[p1] : fmaf(z, P1[p1], a);
+                }
+            }
     }
 }
 
