@@ -56,15 +56,15 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "bdd9e487f4805d75cb3cf4416dc6171e0460f9ed6ad691870770cd9f955ffef2"
+TRAFFIC_SHA256 = "9fadbad584e43ef05bd59cc216ce02d7950f9fd9722cf31cd86156788bc60f1f"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1519314 * 1024, 1.0 * 236740 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3002948 * 1024, 1.0 * 5345221 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2476335 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 3): (2.0 * 1519025 * 1024, 1.0 * 236765 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3004637 * 1024, 1.0 * 5355822 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2466594 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36896 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1071644 * 1024, 1.0 * 254639 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1223644 * 1024, 1.0 * 67191 * 1024),
+    ("project_kernel", 0): (2.0 * 1071105 * 1024, 1.0 * 254649 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1231438 * 1024, 1.0 * 67032 * 1024),
     ("cells_to_coeffs_kernel", 0): (2.0 * 32788 * 1024, 1.0 * 65536 * 1024),
 }
 
