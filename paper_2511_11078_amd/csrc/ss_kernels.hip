@@ -433,9 +433,9 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                 pixel_rect(c0, c1, r0, r1, R, C, mi0, mi1, mj0, mj1);
             }
         }
-        // the view's lines go into the table in segments of whole rows (of
-        // columns, for a row wider than the table); this cell's hits are
-        // queued and integrated when the table or the batch of views is full
+        // the view's lines go into the current half of the table in segments
+        // of whole rows (of columns, for a row wider than a half); this cell's
+        // candidates are queued, and integrated before their half is refilled
         const int W = bi1 - bi0 + 1;
         if (W > 0 && bj1 >= bj0) {
             const int rows_per_seg = max(1, CRAY_HALF / W);
