@@ -56,7 +56,7 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "9fadbad584e43ef05bd59cc216ce02d7950f9fd9722cf31cd86156788bc60f1f"
+TRAFFIC_SHA256 = "6d5adf9efdb0a4452eb381f346f91ab1ac04cdb6aec4f4594e141799f3129237"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
     ("project_kernel", 3): (2.0 * 1519025 * 1024, 1.0 * 236765 * 1024),
