@@ -457,9 +457,12 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
 #pragma unroll
                             for (int m = 32; m >= 1; m >>= 1) K = max(K, __shfl_xor(K, m));
                             const int npop = min(K, count);
+                            int idx = hitq[qhead];  // the next entry's index is read a round ahead
                             for (int k = 0; k < npop; ++k) {
-                                integrate_hit<n>(rays[hitq[qhead]], lo, acc);
                                 qhead = (qhead + 256) & QMASK;
+                                const int cur = idx;
+                                idx = hitq[qhead];
+                                integrate_hit<n>(rays[cur], lo, acc);
                             }
                             count -= npop;
                             __syncthreads();  // no wave reads the other half any more
@@ -498,9 +501,12 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
             ++nviews;
         }
     }
+    int idx = hitq[qhead];
     for (int k = 0; k < count; ++k) {
-        integrate_hit<n>(rays[hitq[qhead]], lo, acc);
         qhead = (qhead + 256) & QMASK;
+        const int cur = idx;
+        idx = hitq[qhead];
+        integrate_hit<n>(rays[cur], lo, acc);
     }
     // moments -> per-basis integrals: apply the blending map along each axis
     if constexpr (n > 0) {
