@@ -56,15 +56,15 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "6d5adf9efdb0a4452eb381f346f91ab1ac04cdb6aec4f4594e141799f3129237"
+TRAFFIC_SHA256 = "483ade421da4c128e400fc9a0b124e6ea113a4b21a0ff902f76d68cfc6033fd0"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1519025 * 1024, 1.0 * 236765 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3004637 * 1024, 1.0 * 5355822 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2466594 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 3): (2.0 * 1519155 * 1024, 1.0 * 236690 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3001021 * 1024, 1.0 * 5353354 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2476218 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36896 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1071105 * 1024, 1.0 * 254649 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1231438 * 1024, 1.0 * 67032 * 1024),
+    ("project_kernel", 0): (2.0 * 1070697 * 1024, 1.0 * 254645 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1230358 * 1024, 1.0 * 66724 * 1024),
     ("cells_to_coeffs_kernel", 0): (2.0 * 32788 * 1024, 1.0 * 65536 * 1024),
 }
 

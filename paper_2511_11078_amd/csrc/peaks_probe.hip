@@ -1,0 +1,133 @@
+// Peak-rate probe of the GPU the transform runs on: a device-to-device copy
+// (HBM bandwidth), independent chains of FP32 FMA in the non-packed form the
+// kernels are compiled to, exp + reciprocal pairs (the sigmoid of the
+// network form's activation) and v_mfma_f32_32x32x16_bf16.  It is a
+// measurement aid for the roofline denominators, separate from the library:
+// `python -m paper_2511_11078_amd.build` builds it next to the library, and
+// it prints one line per rate (best of three launches, HIP events).
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
+
+#define CHECK(x)                                                                              \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) {                                                               \
+            std::fprintf(stderr, "%s failed: %s\n", #x, hipGetErrorString(e_));               \
+            std::exit(1);                                                                     \
+        }                                                                                     \
+    } while (0)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__global__ void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst, long n) {
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+constexpr int CHAINS = 8;
+__global__ void __launch_bounds__(256) fma_kernel(float *out, int iters, float s) {
+    float a[CHAINS];
+    for (int k = 0; k < CHAINS; ++k) a[k] = threadIdx.x * 1e-3f + k;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+#pragma unroll
+            for (int k = 0; k < CHAINS; ++k) a[k] = fmaf(a[k], s, 0.5f);
+    float t = 0.0f;
+    for (int k = 0; k < CHAINS; ++k) t += a[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) sigmoid_kernel(float *out, int iters, float s) {
+    float a[CHAINS];
+    for (int k = 0; k < CHAINS; ++k) a[k] = threadIdx.x * 1e-3f + k * 1e-2f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int k = 0; k < CHAINS; ++k) a[k] = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a[k] * s));
+    float t = 0.0f;
+    for (int k = 0; k < CHAINS; ++k) t += a[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) mfma_kernel(float *out, int iters) {
+    const int lane = threadIdx.x & 63;
+    bf16x8 A, B;
+    for (int k = 0; k < 8; ++k) {
+        A[k] = (__bf16)(1e-3f * (lane + k));
+        B[k] = (__bf16)(1e-3f * (lane - k));
+    }
+    f32x16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
+    for (int it = 0; it < iters; ++it) {
+        c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c2, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c3, 0, 0, 0);
+    }
+    float t = 0.0f;
+    for (int k = 0; k < 16; ++k) t += c0[k] + c1[k] + c2[k] + c3[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+template <class F>
+static float best_ms(F launch) {
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        CHECK(hipEventRecord(e0));
+        launch();
+        CHECK(hipGetLastError());
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms;
+    }
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return best;
+}
+
+int main() {
+    hipDeviceProp_t prop;
+    CHECK(hipGetDeviceProperties(&prop, 0));
+    const int cus = prop.multiProcessorCount;
+    const double simds = 4.0 * cus, clk = 2.4e9;  // MI355X peak engine clock
+    std::printf("device %s, %d compute units, %d MHz reported clock\n", prop.gcnArchName, cus, prop.clockRate / 1000);
+
+    const long bytes = 1L << 30, n4 = bytes / 16;
+    float4 *src = nullptr, *dst = nullptr;
+    CHECK(hipMalloc(&src, bytes));
+    CHECK(hipMalloc(&dst, bytes));
+    CHECK(hipMemset(src, 0, bytes));
+    const float tc = best_ms([&] { copy_kernel<<<cus * 16, 256>>>(src, dst, n4); });
+    std::printf("copy 1 GiB: %.3f ms, %.0f GB/s (read + write)\n", tc, 2.0 * bytes / (tc * 1e-3) / 1e9);
+    CHECK(hipFree(src));
+    CHECK(hipFree(dst));
+
+    const int blocks = cus * 8, threads = 256;
+    float *out = nullptr;
+    CHECK(hipMalloc(&out, sizeof(float) * blocks * threads));
+    const double waves = (double)blocks * threads / 64;
+    const int fit = 2000;
+    const float tf = best_ms([&] { fma_kernel<<<blocks, threads>>>(out, fit, 0.999f); });
+    const double fmas = waves * fit * 16 * CHAINS;
+    std::printf("fp32 fma (non-packed): %.3f ms, %.3f wave instructions per SIMD per cycle at 2.4 GHz, %.1f TFLOP/s\n",
+                tf, fmas / (simds * clk * tf * 1e-3), fmas * 64 * 2 / (tf * 1e-3) / 1e12);
+    const int sit = 500;
+    const float ts = best_ms([&] { sigmoid_kernel<<<blocks, threads>>>(out, sit, 0.7f); });
+    const double trans = waves * sit * 8 * CHAINS * 2;
+    std::printf("exp + rcp: %.3f ms, %.3f wave transcendentals per SIMD per cycle, %.2f T lane results/s\n", ts,
+                trans / (simds * clk * ts * 1e-3), trans * 64 / (ts * 1e-3) / 1e12);
+    const int mit = 2000;
+    const float tm = best_ms([&] { mfma_kernel<<<blocks, threads>>>(out, mit); });
+    const double mflop = waves * mit * 4 * (2.0 * 32 * 32 * 16);
+    std::printf("mfma 32x32x16 bf16: %.3f ms, %.1f TFLOP/s\n", tm, mflop / (tm * 1e-3) / 1e12);
+    CHECK(hipFree(out));
+    return 0;
+}
