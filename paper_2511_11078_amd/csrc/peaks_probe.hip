@@ -26,18 +26,26 @@ __global__ void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-constexpr int CHAINS = 8;
-__global__ void __launch_bounds__(256) fma_kernel(float *out, int iters, float s) {
+constexpr int CHAINS = 16;
+// lane 0 of block 0 also records the shader-clock and the constant 100 MHz
+// real-time counters around its loop (clk[0], clk[1]), giving the clock the
+// FMA stream actually ran at
+__global__ void __launch_bounds__(256) fma_kernel(float *out, int iters, float s, long long *clk) {
+    const long long c0 = clock64(), r0 = wall_clock64();
     float a[CHAINS];
     for (int k = 0; k < CHAINS; ++k) a[k] = threadIdx.x * 1e-3f + k;
     for (int it = 0; it < iters; ++it)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
 #pragma unroll
-            for (int k = 0; k < CHAINS; ++k) a[k] = fmaf(a[k], s, 0.5f);
+            for (int k = 0; k < CHAINS; ++k) a[k] = fmaf(a[k], s, 0.5f);  // independent chains
     float t = 0.0f;
     for (int k = 0; k < CHAINS; ++k) t += a[k];
     out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        clk[0] = clock64() - c0;
+        clk[1] = wall_clock64() - r0;
+    }
 }
 
 __global__ void __launch_bounds__(256) sigmoid_kernel(float *out, int iters, float s) {
@@ -115,10 +123,17 @@ int main() {
     CHECK(hipMalloc(&out, sizeof(float) * blocks * threads));
     const double waves = (double)blocks * threads / 64;
     const int fit = 2000;
-    const float tf = best_ms([&] { fma_kernel<<<blocks, threads>>>(out, fit, 0.999f); });
+    long long *dclk = nullptr, hclk[2] = {0, 0};
+    CHECK(hipMalloc(&dclk, sizeof(hclk)));
+    const float tf = best_ms([&] { fma_kernel<<<blocks, threads>>>(out, fit, 0.999f, dclk); });
+    CHECK(hipMemcpy(hclk, dclk, sizeof(hclk), hipMemcpyDeviceToHost));
+    CHECK(hipFree(dclk));
     const double fmas = waves * fit * 16 * CHAINS;
-    std::printf("fp32 fma (non-packed): %.3f ms, %.3f wave instructions per SIMD per cycle at 2.4 GHz, %.1f TFLOP/s\n",
-                tf, fmas / (simds * clk * tf * 1e-3), fmas * 64 * 2 / (tf * 1e-3) / 1e12);
+    const double ghz = hclk[1] > 0 ? 0.1 * (double)hclk[0] / (double)hclk[1] : 0.0;  // real-time counter: 100 MHz
+    std::printf("fp32 fma (non-packed): %.3f ms, %.3f wave instructions per SIMD per cycle at 2.4 GHz, %.1f TFLOP/s; "
+                "shader clock during the loop %.2f GHz (%.3f per cycle at that clock)\n",
+                tf, fmas / (simds * clk * tf * 1e-3), fmas * 64 * 2 / (tf * 1e-3) / 1e12, ghz,
+                ghz > 0 ? fmas / (simds * ghz * 1e9 * tf * 1e-3) : 0.0);
     const int sit = 500;
     const float ts = best_ms([&] { sigmoid_kernel<<<blocks, threads>>>(out, sit, 0.7f); });
     const double trans = waves * sit * 8 * CHAINS * 2;
