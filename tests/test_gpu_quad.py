@@ -125,6 +125,30 @@ def test_project_single_coefficient(ctxs):
         assert rel_l2(got, want) <= TOL
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("case", ["1x1x1_3x3", "2x1x3_1x1", "1x5x1_1x7"])
+def test_minimal_sizes_both_directions(ctxs, n, case):
+    """Smallest volumes and detectors: bricks holding a single cell row or
+    coefficient, a one-pixel detector, and a single view."""
+    say(f"minimal sizes {case} n={n}")
+    vol, det = case.split("_")
+    dims = tuple(int(t) for t in vol.split("x"))
+    R, C = (int(t) for t in det.split("x"))
+    rng = np.random.default_rng(270 + n)
+    geom = tilted_parallel(1 if case.startswith("2x1x3") else 4, R, C, seed=271, pitch=0.6)
+    c = rng.standard_normal(dims[::-1]).astype(np.float32)
+    got = to_np(ctxs[n].project(to_gpu(c), geom))
+    want = oracle.project(c, geom, n)
+    y = rng.standard_normal(want.shape).astype(np.float32)
+    gb = to_np(ctxs[n].backproject(to_gpu(y), geom, dims))
+    wb = oracle.backproject_subset(y, geom, dims, n)
+    e, eb = rel_l2(got, want), rel_l2(gb, wb)
+    say(f"  forward rel-L2 {e:.3e}, adjoint rel-L2 {eb:.3e}")
+    assert (np.abs(want).max() == 0 or e <= TOL) and (np.abs(wb).max() == 0 or eb <= TOL)
+    if np.abs(want).max() == 0:
+        assert np.abs(got).max() == 0 and np.abs(gb).max() == 0
+
+
 @pytest.mark.parametrize("n", [0, 2, 3])
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
 def test_backproject_all_coefficients(ctxs, n, kind):
