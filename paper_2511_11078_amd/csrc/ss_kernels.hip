@@ -438,7 +438,9 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
         // candidates are queued, and integrated before their half is refilled
         const int W = bi1 - bi0 + 1;
         if (W > 0 && bj1 >= bj0) {
-            const int rows_per_seg = max(1, CRAY_HALF / W);
+            // integer quotients by a float reciprocal: (a + 1/2) / b is at
+            // least 1/(2b) away from an integer, far more than its rounding
+            const int rows_per_seg = max(1, (int)(((float)CRAY_HALF + 0.5f) * __builtin_amdgcn_rcpf((float)W)));
             const int cols = min(W, CRAY_HALF);
             for (int cj0 = bj0; cj0 <= bj1; cj0 += rows_per_seg) {
                 const int cj1 = min(bj1, cj0 + rows_per_seg - 1);
@@ -475,8 +477,10 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                     }
                     // new entries go past every queued one: no barrier needed
                     const int tb = half * CRAY_HALF + used;  // first table entry of the segment
+                    const float rcw = __builtin_amdgcn_rcpf((float)cw);
                     for (int t = tid; t < cn; t += blockDim.x) {
-                        const int jj = cj0 + t / cw, ii = ci0 + t % cw;
+                        const int q = (int)(((float)t + 0.5f) * rcw);
+                        const int jj = cj0 + q, ii = ci0 + (t - q * cw);
                         fill_cellray(rays[tb + t], e, kind, R, C, jj, ii, centre,
                                      y[((int64_t)v * R + jj) * C + ii]);
                     }

@@ -54,6 +54,11 @@ __device__ __forceinline__ bool fwd_block_tile(int V, int tR, int tC, int &v, in
 struct ViewProj {    // detector coordinates of a world point (FP64 set-up)
     double d0[3], s[3], du_s[3], dv_s[3], nrm[3];
     double plane;    // (d0 - s) . nrm  (cone)
+    // for make_localproj: o . du_s, o . dv_s, o . nrm with o = s (cone) or d0
+    // (parallel), and the FP32 values that do not depend on the centre
+    double odu, odv, onm;
+    float du_f[3], dv_f[3], nm_f[3];
+    float ac_f, ar_f, plane_f;  // (s - d0) . du_s, (s - d0) . dv_s, plane
     int kind;
 };
 
@@ -108,6 +113,21 @@ __host__ __device__ inline void make_viewproj(const float *__restrict__ e, int k
         P.du_s[k] = c0[k] * id;
         P.dv_s[k] = c1[k] * id;
     }
+    double o[3], sd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[k] = kind == 0 ? P.d0[k] : P.s[k];
+        sd[k] = P.s[k] - P.d0[k];
+        P.du_f[k] = (float)P.du_s[k];
+        P.dv_f[k] = (float)P.dv_s[k];
+        P.nm_f[k] = (float)P.nrm[k];
+    }
+    P.odu = o[0] * P.du_s[0] + o[1] * P.du_s[1] + o[2] * P.du_s[2];
+    P.odv = o[0] * P.dv_s[0] + o[1] * P.dv_s[1] + o[2] * P.dv_s[2];
+    P.onm = o[0] * P.nrm[0] + o[1] * P.nrm[1] + o[2] * P.nrm[2];
+    P.ac_f = (float)(sd[0] * P.du_s[0] + sd[1] * P.du_s[1] + sd[2] * P.du_s[2]);
+    P.ar_f = (float)(sd[0] * P.dv_s[0] + sd[1] * P.dv_s[1] + sd[2] * P.dv_s[2]);
+    P.plane_f = (float)P.plane;
 }
 
 // Detector coordinates of points X = c + delta near a centre c, evaluated in
@@ -124,22 +144,21 @@ struct LocalProj {
     int kind;
 };
 
+// D . du_s = c . du_s - o . du_s in FP64 (three FMA and a difference per
+// term); everything else comes from the view's set-up.
 __device__ __forceinline__ void make_localproj(const ViewProj &P, const double c[3], LocalProj &L) {
-    double D[3], sd[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        D[k] = c[k] - (P.kind == 0 ? P.d0[k] : P.s[k]);
-        sd[k] = P.s[k] - P.d0[k];
-        L.du[k] = (float)P.du_s[k];
-        L.dv[k] = (float)P.dv_s[k];
-        L.nm[k] = (float)P.nrm[k];
+        L.du[k] = P.du_f[k];
+        L.dv[k] = P.dv_f[k];
+        L.nm[k] = P.nm_f[k];
     }
-    L.nc = (float)(D[0] * P.du_s[0] + D[1] * P.du_s[1] + D[2] * P.du_s[2]);
-    L.nr = (float)(D[0] * P.dv_s[0] + D[1] * P.dv_s[1] + D[2] * P.dv_s[2]);
-    L.dn = (float)(D[0] * P.nrm[0] + D[1] * P.nrm[1] + D[2] * P.nrm[2]);
-    L.ac = (float)(sd[0] * P.du_s[0] + sd[1] * P.du_s[1] + sd[2] * P.du_s[2]);
-    L.ar = (float)(sd[0] * P.dv_s[0] + sd[1] * P.dv_s[1] + sd[2] * P.dv_s[2]);
-    L.plane = (float)P.plane;
+    L.nc = (float)(fma(c[2], P.du_s[2], fma(c[1], P.du_s[1], c[0] * P.du_s[0])) - P.odu);
+    L.nr = (float)(fma(c[2], P.dv_s[2], fma(c[1], P.dv_s[1], c[0] * P.dv_s[0])) - P.odv);
+    L.dn = (float)(fma(c[2], P.nrm[2], fma(c[1], P.nrm[1], c[0] * P.nrm[0])) - P.onm);
+    L.ac = P.ac_f;
+    L.ar = P.ar_f;
+    L.plane = P.plane_f;
     L.kind = P.kind;
 }
 
