@@ -56,16 +56,16 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "483ade421da4c128e400fc9a0b124e6ea113a4b21a0ff902f76d68cfc6033fd0"
+TRAFFIC_SHA256 = "bc2bbaaf460170b219b4428e3873a94368109ec65c3e4334404ea35ef5bc388f"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1519155 * 1024, 1.0 * 236690 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3001021 * 1024, 1.0 * 5353354 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2476218 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 3): (2.0 * 1519407 * 1024, 1.0 * 236711 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3017116 * 1024, 1.0 * 5392302 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2473610 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36896 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1070697 * 1024, 1.0 * 254645 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1230358 * 1024, 1.0 * 66724 * 1024),
-    ("cells_to_coeffs_kernel", 0): (2.0 * 32788 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 0): (2.0 * 1069404 * 1024, 1.0 * 254570 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1247318 * 1024, 1.0 * 66928 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32780 * 1024, 1.0 * 65536 * 1024),
 }
 
 
