@@ -21,8 +21,11 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SRC / ORACLE_LIB name another copy of the C source and its library:
+# the mutation test uses them to run the pins against deliberately broken
+# copies (tests/test_oracle_mutations.py)
+_SRC = os.environ.get("ORACLE_SRC") or os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _KIND = {"parallel": 0, "cone": 1}
