@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // candidate pixels (about 95 % of them hit the cell).  A thread queues its
 // candidates without reading their lines in a ring, oldest first, and the
 // integration drops the few whose chord through the cell is empty.  The
-// table has two halves filled in turn (up to VIEWS_PER_HALF views each):
+// table has two halves filled in turn (up to a few views each):
 // before a half is refilled, each wave runs as many integration rounds as
 // its lane with the most entries in that half needs, and lanes with fewer
 // take entries of the other half in the same rounds, so that the lanes of a
@@ -221,9 +221,15 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // ---------------------------------------------------------------------------
 constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
-constexpr int CRAY_CAP = 832;                   // lines in the LDS table (two halves)
-constexpr int CRAY_HALF = CRAY_CAP / 2;
-constexpr int VIEWS_PER_HALF = 5;               // views whose lines fill one half
+// Line table (two halves) and occupancy per degree: the cubic kernel's
+// registers allow three waves per SIMD, so its table takes what LDS leaves
+// for three blocks per CU; lower degrees fit four waves and a smaller table.
+template <int n> struct CellGather {
+    static constexpr int waves = n == 3 ? 3 : 4;          // waves per SIMD: blocks per CU
+    static constexpr int cap = n == 3 ? 832 : 512;        // lines in the LDS table
+    static constexpr int half = cap / 2;
+    static constexpr int views_per_half = n == 3 ? 5 : 3;
+};
 constexpr int HITQ_CAP = 32;                    // queued candidates per thread (a ring)
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
@@ -348,10 +354,11 @@ __device__ __forceinline__ void corner_bounds(const float2 *corner, int sx, int 
     }
 }
 
-// Three waves per SIMD (at most 168 VGPRs) keep three blocks on a CU to hide
-// the per-view set-up between barriers.
+// Three (degree 3, at most 168 VGPRs) or four (lower degrees, 128) waves per
+// SIMD keep as many blocks on a CU, to hide the per-view set-up between
+// barriers behind other blocks' integration.
 template <int n>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CellGather<n>::waves)))
 backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, const float *__restrict__ geom,
                          const ViewProj *__restrict__ vps, int kind, int V, int R, int C, int mz0, int L,
                          float *__restrict__ T) {
@@ -359,7 +366,8 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     constexpr int NB = n + 1;
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
-    __shared__ CellRay rays[CRAY_CAP];
+    constexpr int CRAY_HALF = CellGather<n>::half, VIEWS_PER_HALF = CellGather<n>::views_per_half;
+    __shared__ CellRay rays[CellGather<n>::cap];
     __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of candidate table indices
     __shared__ float2 corner[NCORNER];
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
