@@ -144,9 +144,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py measures one GPU only: the transform is built and measured on a single MI355X; "
+        print(f"bench.py measures one GPU only: the library runs the transform on a single MI355X; "
               f"--gpus {args.gpus} is not supported (views would be sharded across GPUs with an all-reduce "
-              f"of the back-projected volume, which this build does not implement).", file=sys.stderr)
+              f"of the back-projected volume, which the library does not implement).", file=sys.stderr)
         sys.exit(2)
 
     import torch
