@@ -37,11 +37,6 @@ sys.path.insert(0, ROOT)
 METRIC = "forward+adjoint rays/s at 256³ cone-beam (MLP vs quadrature footprint), rel-L2"
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # 256 CU x 128 FP32 FMA/clk (packed) x 2 x 2.4 GHz
-# The kernels are compiled without packed FP32 instructions: one wave64 FMA
-# per SIMD every four cycles, 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz.
-# Reported beside the published peak (never in its place) as the ceiling of
-# the instruction mix these kernels are built with.
-CEIL_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 GL_ORDER = {0: 1, 1: 2, 2: 4, 3: 5}
 
@@ -282,9 +277,7 @@ def main():
                 kernels.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
                                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                 "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit,
-                                "traffic": measured_traffic(knames, n, wl.name),
-                                "ceiling_nonpacked_fp32": CEIL_FP32_NONPACKED_TFLOPS,
-                                "frac_of_nonpacked_ceiling": ach / CEIL_FP32_NONPACKED_TFLOPS})
+                                "traffic": measured_traffic(knames, n, wl.name)})
         else:
             fl = total_pairs * MLP_FLOPS_PER_PAIR
             for name, ms in ((f"project_mlp_kernel<{n}>", r0["fwd_ms"]), (f"backproject_mlp_kernel<{n}>", r0["adj_ms"])):
@@ -298,9 +291,6 @@ def main():
                            "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
                            "kernel": dom["kernel"],
                            "kernel_ms": dom["ms"], "work": dom["work"]}
-        for key in ("ceiling_nonpacked_fp32", "frac_of_nonpacked_ceiling"):
-            if key in dom:
-                out["roofline"][key] = dom[key]
         out["kernels"] = kernels
         out["work_counts"] = {"sample_lines": int(cnt_rays.size), "pairs_per_line": pairs_per_ray,
                               "segments_per_pair": segs_per_pair, "cells_per_line": cells_per_ray,
