@@ -57,12 +57,13 @@ def test_parallel_128_quad():
     assert ef <= TOL_QUAD and eb <= TOL_QUAD
 
 
-def test_parallel_128_dot_test():
-    say("parallel_128 dot test")
-    wl = configs.get("parallel_128")
+def _dot_test(wl_name, seed):
+    """<A x, y> = <x, A^T y> for noise x and y over the whole workload (the
+    adjoint is the exact transpose, so only FP32 rounding separates them)."""
+    wl = configs.get(wl_name)
     geom = wl.geometry()
-    ctx = Context(3, "quad", 0)
-    rng = np.random.default_rng(5)
+    ctx = Context(wl.degree, "quad", 0)
+    rng = np.random.default_rng(seed)
     x = to_gpu(rng.standard_normal(wl.dims[::-1]).astype(np.float32))
     y = to_gpu(rng.standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32))
     Ax = ctx.project(x, geom)
@@ -70,8 +71,19 @@ def test_parallel_128_dot_test():
     lhs = float((Ax.double() * y.double()).sum())
     rhs = float((x.double() * Aty.double()).sum())
     rel = abs(lhs - rhs) / (float(Ax.double().norm()) * float(y.double().norm()))
-    say(f"  dot-test relative mismatch {rel:.3e}")
-    assert rel <= 1e-5
+    say(f"  {wl_name} dot-test relative mismatch {rel:.3e}")
+    ctx.close()
+    return rel
+
+
+def test_parallel_128_dot_test():
+    say("parallel_128 dot test")
+    assert _dot_test("parallel_128", 5) <= 1e-5
+
+
+def test_cone_256_dot_test():
+    say("cone_256 dot test")
+    assert _dot_test("cone_256", 6) <= 1e-5
 
 
 def test_cone_256_quad():
