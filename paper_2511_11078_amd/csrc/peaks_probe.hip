@@ -1,10 +1,12 @@
 // Peak-rate probe of the GPU the transform runs on: a device-to-device copy
 // (HBM bandwidth), independent chains of FP32 FMA in the non-packed form the
-// kernels are compiled to, exp + reciprocal pairs (the sigmoid of the
-// network form's activation) and v_mfma_f32_32x32x16_bf16.  It is a
-// measurement aid for the roofline denominators, separate from the library:
-// `python -m paper_2511_11078_amd.build` builds it next to the library, and
-// it prints one line per rate (best of three launches, HIP events).
+// kernels are compiled to (once with a scalar-register operand, once with
+// vector-register operands only: the two issue at different rates), exp +
+// reciprocal pairs (the sigmoid of the network form's activation) and
+// v_mfma_f32_32x32x16_bf16.  It is a measurement aid for the roofline
+// denominators, separate from the library: `python -m
+// paper_2511_11078_amd.build` builds it next to the library, and it prints
+// one line per rate (best of three launches, HIP events).
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdlib>
@@ -46,6 +48,25 @@ __global__ void __launch_bounds__(256) fma_kernel(float *out, int iters, float s
         clk[0] = clock64() - c0;
         clk[1] = wall_clock64() - r0;
     }
+}
+
+// the same chains with every operand in a vector register (per-lane
+// multiplier and addend), as in the transform's own arithmetic
+__global__ void __launch_bounds__(256) fma_vgpr_kernel(float *out, int iters, float s) {
+    float a[CHAINS], b[CHAINS], c[CHAINS];
+    for (int k = 0; k < CHAINS; ++k) {
+        a[k] = threadIdx.x * 1e-3f + k;
+        b[k] = s + 1e-7f * (float)((threadIdx.x & 7) * k);
+        c[k] = 0.5f + 1e-3f * (float)((threadIdx.x & 3) * k);
+    }
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+#pragma unroll
+            for (int k = 0; k < CHAINS; ++k) a[k] = fmaf(a[k], b[k], c[k]);
+    float t = 0.0f;
+    for (int k = 0; k < CHAINS; ++k) t += a[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
 __global__ void __launch_bounds__(256) sigmoid_kernel(float *out, int iters, float s) {
@@ -130,10 +151,18 @@ int main() {
     CHECK(hipFree(dclk));
     const double fmas = waves * fit * 16 * CHAINS;
     const double ghz = hclk[1] > 0 ? 0.1 * (double)hclk[0] / (double)hclk[1] : 0.0;  // real-time counter: 100 MHz
-    std::printf("fp32 fma (non-packed): %.3f ms, %.3f wave instructions per SIMD per cycle at 2.4 GHz, %.1f TFLOP/s; "
-                "shader clock during the loop %.2f GHz (%.3f per cycle at that clock)\n",
+    std::printf("fp32 fma (non-packed), scalar-register operand: %.3f ms, %.3f wave instructions per SIMD per cycle "
+                "at 2.4 GHz, %.1f TFLOP/s; shader clock during the loop %.2f GHz (%.3f per cycle at that clock)\n",
                 tf, fmas / (simds * clk * tf * 1e-3), fmas * 64 * 2 / (tf * 1e-3) / 1e12, ghz,
                 ghz > 0 ? fmas / (simds * ghz * 1e9 * tf * 1e-3) : 0.0);
+    // at most eight, and at most four, waves per SIMD: the same blocks, four
+    // of them per CU when each asks for 38 KiB of (unused) LDS
+    for (int lds : {0, 38 * 1024}) {
+        const float tv = best_ms([&] { fma_vgpr_kernel<<<blocks, threads, lds>>>(out, fit, 0.999f); });
+        std::printf("fp32 fma (non-packed), vector-register operands only, %d waves per SIMD: %.3f ms, %.3f wave "
+                    "instructions per SIMD per cycle at 2.4 GHz, %.1f TFLOP/s\n",
+                    lds ? 4 : 8, tv, fmas / (simds * clk * tv * 1e-3), fmas * 64 * 2 / (tv * 1e-3) / 1e12);
+    }
     const int sit = 500;
     const float ts = best_ms([&] { sigmoid_kernel<<<blocks, threads>>>(out, sit, 0.7f); });
     const double trans = waves * sit * 8 * CHAINS * 2;
