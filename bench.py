@@ -56,15 +56,15 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "67d2433354392fd2e6d04b454c41e68f8a53cb044b0b2505c4d3de785b45673e"
+TRAFFIC_SHA256 = "078465f0b711d62c90e55b6c966613e0bd8dc6d1b1705ae690d79be50d142dc9"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("pad_volume_kernel", 3): (2.0 * 36900 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1518924 * 1024, 1.0 * 236877 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3016535 * 1024, 1.0 * 5377892 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2479536 * 1024, 1.0 * 65536 * 1024),
+    ("pad_volume_kernel", 3): (2.0 * 36895 * 1024, 1.0 * 71874 * 1024),
+    ("project_kernel", 3): (2.0 * 1529681 * 1024, 1.0 * 228822 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3016593 * 1024, 1.0 * 5393433 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2485279 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36896 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1069106 * 1024, 1.0 * 254571 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1242820 * 1024, 1.0 * 67483 * 1024),
+    ("project_kernel", 0): (2.0 * 1070964 * 1024, 1.0 * 254721 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1244836 * 1024, 1.0 * 67755 * 1024),
     ("cells_to_coeffs_kernel", 0): (2.0 * 32780 * 1024, 1.0 * 65536 * 1024),
 }
 

@@ -701,8 +701,14 @@ static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     const int pb = (int)std::min<int64_t>((padded + 255) / 256, 65536);
     hipLaunchKernelGGL(pad_volume_kernel, dim3(pb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1], a.N[2], P,
                        a.scratch);
-    hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), 0, st, a.scratch, a.N[0], a.N[1], a.N[2], a.geom,
-                       a.kind, a.V, a.R, a.C, a.sino);
+    // Occupancy of the walk: for degrees 1..3 a block reserves LDS it does
+    // not use (FWD_IDLE_LDS), so that at most three blocks, three waves per
+    // SIMD, share a CU.  Fewer concurrent walks then share the CU's L1
+    // cache, which keeps more of each wave's coefficient rows; the degree-0
+    // walk (one coefficient per cell) runs best at full occupancy.
+    constexpr int FWD_IDLE_LDS = n == 0 ? 0 : 50 * 1024;  // 3 x 50 KiB of the CU's 160 KiB
+    hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), FWD_IDLE_LDS, st, a.scratch, a.N[0], a.N[1],
+                       a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino);
     return hipGetLastError();
 }
 
