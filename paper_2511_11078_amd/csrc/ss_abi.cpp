@@ -15,19 +15,15 @@
 #include <vector>
 
 #include "splinesplat.h"
+#include "ss_geom_upload.hpp"
 #include "ss_kernels.hpp"
 
 struct ss_ctx {
     int device = 0;
     int degree = 3;
     int form = SS_FORM_QUAD_FP32;
-    float *d_geom = nullptr;        // device copy of the last geometry
-    size_t geom_cap = 0;            // floats
-    float *h_stage = nullptr;       // pinned staging for uploads
-    hipEvent_t staged = nullptr;    // last upload read from h_stage
-    bool staged_pending = false;
-    std::vector<float> last_vecs;   // host copy of the view vectors d_geom holds
-    int last_kind = -1;             // and their geometry kind
+    ss::GeomBuffer geom;            // device copy of the last geometry, pinned staging, upload cache
+    hipEvent_t staged = nullptr;    // marks the end of the last upload's read of the staging buffer
     double *d_partials = nullptr;   // dot-product partial sums
     void *d_mlp = nullptr;          // network weights in kernel layout
     float *d_cells = nullptr;       // quadrature scratch: padded coefficients (forward), knot-cell table (adjoint)
@@ -133,56 +129,47 @@ ss_status check_geom(const ss_geometry *g) {
 // Float offset of the per-view projections behind the view vectors.
 size_t vproj_offset(size_t n_views) { return (n_views * 12 + 3) / 4 * 4; }
 
+// HIP device operations of the geometry upload (ss_geom_upload.hpp).
+struct HipUploadOps {
+    hipStream_t st;
+    hipEvent_t ev;
+    int dev_alloc(void **p, size_t bytes) { return (int)hipMalloc(p, bytes); }
+    void dev_free(void *p) { (void)hipFree(p); }
+    int host_alloc(void **p, size_t bytes) { return (int)hipHostMalloc(p, bytes, hipHostMallocDefault); }
+    void host_free(void *p) { (void)hipHostFree(p); }
+    int device_sync() { return (int)hipDeviceSynchronize(); }
+    int event_sync() { return (int)hipEventSynchronize(ev); }
+    int copy_async(void *dst, const void *src, size_t bytes) {
+        return (int)hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    }
+    int event_record() { return (int)hipEventRecord(ev, st); }
+};
+
 // Upload the geometry if it differs from what the device buffer holds: the
 // view vectors, followed by each view's detector projection (FP64, computed
 // here once instead of by every block of the adjoint at every view).
 ss_status upload_geom(ss_ctx *ctx, const ss_geometry *g, hipStream_t st) {
     const size_t nv = (size_t)g->n_views;
     const size_t nf = nv * 12;
-    if (ctx->last_vecs.size() == nf && ctx->last_kind == (int)g->kind &&
-        std::memcmp(ctx->last_vecs.data(), g->vecs, nf * sizeof(float)) == 0)
-        return SS_OK;
     const size_t vp_off = vproj_offset(nv);
     const size_t total = vp_off + nv * (sizeof(ss::ViewProj) / sizeof(float));
-    hipError_t e;
-    if (total > ctx->geom_cap) {
-        // the old buffers may still be read by enqueued work: wait for it
-        if (ctx->d_geom || ctx->h_stage) {
-            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-            (void)hipFree(ctx->d_geom);
-            (void)hipHostFree(ctx->h_stage);
-            ctx->d_geom = nullptr;
-            ctx->h_stage = nullptr;
-            ctx->staged_pending = false;
-        }
-        size_t cap = total < 4096 ? 4096 : total;
-        if ((e = hipMalloc(&ctx->d_geom, cap * sizeof(float))) != hipSuccess) {
-            ctx->geom_cap = 0;
-            return fail(SS_ENOMEM, "geometry buffer: %s", hipGetErrorString(e));
-        }
-        if ((e = hipHostMalloc(&ctx->h_stage, cap * sizeof(float), hipHostMallocDefault)) != hipSuccess) {
-            (void)hipFree(ctx->d_geom);
-            ctx->d_geom = nullptr;
-            ctx->geom_cap = 0;
-            return fail(SS_ENOMEM, "geometry staging: %s", hipGetErrorString(e));
-        }
-        ctx->geom_cap = cap;
+    HipUploadOps ops{st, ctx->staged};
+    auto fill = [&](float *stage) {
+        ss::ViewProj *vp = reinterpret_cast<ss::ViewProj *>(stage + vp_off);
+        for (size_t v = 0; v < nv; ++v) ss::make_viewproj(g->vecs + 12 * v, (int)g->kind, vp[v]);
+    };
+    int code = 0;
+    const ss::UploadError r = ctx->geom.upload(ops, g->vecs, nf, (int)g->kind, total, fill, &code);
+    const char *msg = hipGetErrorString((hipError_t)code);
+    switch (r) {
+    case ss::UPLOAD_OK: return SS_OK;
+    case ss::UPLOAD_SYNC: return fail(SS_EDEVICE, "geometry upload: synchronisation: %s", msg);
+    case ss::UPLOAD_DEV_ALLOC: return fail(SS_ENOMEM, "geometry buffer: %s", msg);
+    case ss::UPLOAD_HOST_ALLOC: return fail(SS_ENOMEM, "geometry staging: %s", msg);
+    case ss::UPLOAD_COPY: return fail(SS_EDEVICE, "geometry upload: %s", msg);
+    case ss::UPLOAD_EVENT: return fail(SS_EDEVICE, "geometry upload: hipEventRecord: %s", msg);
     }
-    if (ctx->staged_pending) {
-        if ((e = hipEventSynchronize(ctx->staged)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        ctx->staged_pending = false;
-    }
-    std::memcpy(ctx->h_stage, g->vecs, nf * sizeof(float));
-    ss::ViewProj *vp = reinterpret_cast<ss::ViewProj *>(ctx->h_stage + vp_off);
-    for (size_t v = 0; v < nv; ++v) ss::make_viewproj(g->vecs + 12 * v, (int)g->kind, vp[v]);
-    if ((e = hipMemcpyAsync(ctx->d_geom, ctx->h_stage, total * sizeof(float), hipMemcpyHostToDevice, st)) !=
-        hipSuccess)
-        return hip_fail(e, "geometry upload");
-    if ((e = hipEventRecord(ctx->staged, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ctx->staged_pending = true;
-    ctx->last_vecs.assign(g->vecs, g->vecs + nf);
-    ctx->last_kind = (int)g->kind;
-    return SS_OK;
+    return fail(SS_EDEVICE, "geometry upload failed");
 }
 
 // Make the quadrature scratch (padded coefficients for the forward, the
@@ -281,10 +268,12 @@ ss_status ss_create(ss_ctx **out, int device, int degree, ss_form form, const vo
 ss_status ss_destroy(ss_ctx *ctx) {
     if (!ctx) return SS_OK;
     DeviceGuard guard(ctx->device);
-    if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
+    if (ctx->geom.staged_pending) (void)hipEventSynchronize(ctx->staged);
+    {
+        HipUploadOps ops{nullptr, ctx->staged};
+        ctx->geom.release(ops);
+    }
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
-    if (ctx->d_geom) (void)hipFree(ctx->d_geom);
-    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     if (ctx->d_mlp) (void)hipFree(ctx->d_mlp);
     if (ctx->d_cells) (void)hipFree(ctx->d_cells);
@@ -304,8 +293,8 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
     hipStream_t st = (hipStream_t)hip_stream;
     if (ss_status s = upload_geom(ctx, geom, st)) return s;
     ss::LaunchArgs a{};
-    a.geom = ctx->d_geom;
-    a.vproj = reinterpret_cast<const ss::ViewProj *>(ctx->d_geom + vproj_offset((size_t)geom->n_views));
+    a.geom = ctx->geom.d_geom;
+    a.vproj = reinterpret_cast<const ss::ViewProj *>(ctx->geom.d_geom + vproj_offset((size_t)geom->n_views));
     a.N[0] = (int)dims[0];
     a.N[1] = (int)dims[1];
     a.N[2] = (int)dims[2];

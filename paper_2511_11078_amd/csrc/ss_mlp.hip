@@ -4,8 +4,10 @@
 // Precision split: fold, frame and layer 1 in FP32 (layer 1 on the FP32
 // matrix core, v_mfma_f32_32x32x2_f32); the three 64x64 layers on the BF16
 // matrix core with FP32 accumulation (v_mfma_f32_32x32x16_bf16); SiLU in
-// FP32, its result rounded to BF16 (nearest even) when it feeds a BF16 layer;
-// output layer in FP32.  The network value is multiplied by the indicator
+// FP32; an activation feeding a BF16 layer is carried as the sum of two BF16
+// numbers (its rounding to nearest even and the rounding of the remainder),
+// so each such layer is two BF16 products into one FP32 accumulator and the
+// activations keep about 16 significant bits; output layer in FP32.  The network value is multiplied by the indicator
 // that the line meets the basis support (exact slab test), so the pair set
 // equals the quadrature form's.
 //
@@ -163,13 +165,17 @@ __device__ __forceinline__ float mlp_tile(const MlpImage &W, float f0, float f1,
     }
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
-        bf16x8 B[4];
+        // each activation as the sum of two BF16 numbers: hi = RNE(a),
+        // lo = RNE(a - hi); the layer is W hi + W lo in one FP32 accumulator
+        bf16x8 Bh[4], Bl[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             f32x8 v;
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] = silu(kk < 2 ? acc0[8 * kk + e] : acc1[8 * (kk - 2) + e]);
-            B[kk] = __builtin_convertvector(v, bf16x8);
+            Bh[kk] = __builtin_convertvector(v, bf16x8);
+            const f32x8 back = __builtin_convertvector(Bh[kk], f32x8);
+            Bl[kk] = __builtin_convertvector(v - back, bf16x8);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -180,8 +186,10 @@ __device__ __forceinline__ float mlp_tile(const MlpImage &W, float f0, float f1,
         for (int kk = 0; kk < 4; ++kk) {
             const bf16x8 A0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(W.wh[L][0][kk][lane]));
             const bf16x8 A1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(W.wh[L][1][kk][lane]));
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B[kk], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B[kk], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Bh[kk], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Bh[kk], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Bl[kk], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Bl[kk], acc1, 0, 0, 0);
         }
     }
     float part = 0.0f;

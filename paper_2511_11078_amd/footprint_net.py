@@ -15,14 +15,19 @@ five features are (w1, w2, w3, u.x, v.x); x is any point of the line relative
 to the basis centre.
 
 Precision split used by the GPU kernel: fold, frame and layer 1 in FP32; the
-three 64x64 layers take BF16 operands with FP32 accumulation; SiLU in FP32;
-the output layer in FP32.  The kernel multiplies the network output by the
+three 64x64 layers take BF16 operands with FP32 accumulation -- the weights
+are BF16 numbers, and each FP32 activation entering such a layer is carried
+as the sum of two BF16 numbers (its rounding and the rounding of what that
+leaves), so the layer is two BF16 products into one FP32 accumulator and
+the activations lose about 16 bits instead of 8; SiLU in FP32; the output
+layer in FP32.  The kernel multiplies the network output by the
 indicator that the line meets the basis support (an exact slab test), so the
 network is only ever used where the true footprint can be non-zero.
 
 Training labels come from ``exact_footprint`` below: an FP64 vectorised
 piecewise Gauss-Legendre integral (exact for B-splines, see the module
-docstring of ``train_footprint``), written for training only.
+docstring of ``train_footprint``), written for training only; it runs on
+the host or, during training, on the GPU.
 """
 from __future__ import annotations
 
@@ -47,87 +52,116 @@ def blob_bytes() -> int:
 
 
 # --------------------------------------------------------------------------
-# folding and features (numpy, FP64 -- for training data)
+# folding, features and FP64 training labels.  Each is written once with
+# torch operations, so that it runs on the host (numpy in, numpy out) and on
+# a GPU during training (torch tensors in, torch tensors out).
 # --------------------------------------------------------------------------
-def fold_features(w: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """(w, x) [B, 3] -> features [B, 5] of fold convention 1."""
-    w = np.asarray(w, dtype=np.float64)
-    x = np.asarray(x, dtype=np.float64)
-    aw = np.abs(w)
-    perm = np.argsort(aw, axis=1, kind="stable")          # ascending |w|
-    rows = np.arange(w.shape[0])[:, None]
-    sgn = np.where(w[rows, perm] < 0, -1.0, 1.0)
-    wf = aw[rows, perm]
-    xf = x[rows, perm] * sgn
+def _as_torch(a):
+    import torch
+
+    if isinstance(a, torch.Tensor):
+        return a.to(torch.float64), False
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)), True
+
+
+def fold_features(w, x):
+    """(w, x) [B, 3] -> features [B, 5] of fold convention 1: sort |w|
+    ascending (stable: lower axis first on ties), apply the same signed
+    permutation to x, frame u = normalise(e1 - w1 w), v = u x w."""
+    import torch
+
+    w, to_np = _as_torch(w)
+    x, _ = _as_torch(x)
+    aw = w.abs()
+    perm = torch.argsort(aw, dim=1, stable=True)
+    wsel = torch.gather(w, 1, perm)
+    sgn = torch.where(wsel < 0, -1.0, 1.0).to(w.dtype)
+    wf = torch.gather(aw, 1, perm)
+    xf = torch.gather(x, 1, perm) * sgn
     u = -wf[:, 0:1] * wf
     u[:, 0] += 1.0
-    u /= np.linalg.norm(u, axis=1, keepdims=True)
-    v = np.cross(u, wf)
-    return np.concatenate([wf, (u * xf).sum(1, keepdims=True), (v * xf).sum(1, keepdims=True)], axis=1)
+    u = u / torch.linalg.norm(u, dim=1, keepdim=True)
+    v = torch.linalg.cross(u, wf, dim=1)
+    out = torch.cat([wf, (u * xf).sum(1, keepdim=True), (v * xf).sum(1, keepdim=True)], dim=1)
+    return out.numpy() if to_np else out
 
 
-def chord_nonempty(n: int, w: np.ndarray, x: np.ndarray) -> np.ndarray:
+def _chord(n: int, w, x):
+    """Parameter interval (t0, t1) of the line x + t w inside the open
+    support cube (-h, h)^3, and whether it is non-empty."""
+    import torch
+
     h = 0.5 * (n + 1)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ta = (-h - x) / w
-        tb = (h - x) / w
-    lo = np.where(w == 0, np.where(np.abs(x) < h, -np.inf, np.inf), np.minimum(ta, tb))
-    hi = np.where(w == 0, np.where(np.abs(x) < h, np.inf, -np.inf), np.maximum(ta, tb))
-    return lo.max(1) < hi.min(1)
+    inside = x.abs() < h
+    ta = (-h - x) / w
+    tb = (h - x) / w
+    inf = torch.full_like(x, float("inf"))
+    lo = torch.where(w == 0, torch.where(inside, -inf, inf), torch.minimum(ta, tb))
+    hi = torch.where(w == 0, torch.where(inside, inf, -inf), torch.maximum(ta, tb))
+    t0 = lo.max(1).values
+    t1 = hi.min(1).values
+    return t0, t1, t0 < t1
 
 
-# --------------------------------------------------------------------------
-# FP64 training labels
-# --------------------------------------------------------------------------
-def _bspline(n: int, x: np.ndarray) -> np.ndarray:
-    a = np.abs(x)
+def chord_nonempty(n: int, w, x):
+    w, to_np = _as_torch(w)
+    x, _ = _as_torch(x)
+    ok = _chord(n, w, x)[2]
+    return ok.numpy() if to_np else ok
+
+
+def _bspline(n: int, x):
+    import torch
+
+    a = x.abs()
     if n == 0:
-        return (a < 0.5).astype(np.float64)
+        return (a < 0.5).to(x.dtype)
     if n == 1:
-        return np.maximum(1.0 - a, 0.0)
+        return torch.clamp(1.0 - a, min=0.0)
     if n == 2:
-        return np.where(a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+        return torch.where(a < 0.5, 0.75 - a * a, torch.where(a < 1.5, 0.5 * (1.5 - a) ** 2, torch.zeros_like(a)))
     if n == 3:
-        return np.where(a < 1.0, 2.0 / 3.0 - a * a + 0.5 * a ** 3, np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+        return torch.where(a < 1.0, 2.0 / 3.0 - a * a + 0.5 * a ** 3,
+                           torch.where(a < 2.0, (2.0 - a) ** 3 / 6.0, torch.zeros_like(a)))
     raise ValueError(n)
 
 
-def exact_footprint(n: int, w: np.ndarray, x: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+def exact_footprint(n: int, w, x, chunk: int = 1 << 16):
     """int phi(x + t w) dt for unit w, in FP64: clip to the support cube, cut
     at the interior knot planes, Gauss-Legendre of order ceil((3n+1)/2) on
-    each piece (exact, the integrand being a polynomial of degree 3n there)."""
-    w = np.asarray(w, dtype=np.float64)
-    x = np.asarray(x, dtype=np.float64)
-    out = np.empty(w.shape[0])
+    each piece (exact, the integrand being a polynomial of degree 3n there).
+    numpy arrays in -> numpy out (host); torch tensors in -> torch out on
+    their device."""
+    import torch
+
+    w, to_np = _as_torch(w)
+    x, _ = _as_torch(x)
+    dev = w.device
+    out = torch.empty(w.shape[0], dtype=torch.float64, device=dev)
     h = 0.5 * (n + 1)
     m = max(1, (3 * n + 2) // 2)
-    gx, gw = np.polynomial.legendre.leggauss(m)
-    knots = -h + np.arange(1, n + 1, dtype=np.float64)
+    gx_np, gw_np = np.polynomial.legendre.leggauss(m)
+    gx = torch.from_numpy(gx_np).to(dev)
+    gw = torch.from_numpy(gw_np).to(dev)
+    knots = (-h + torch.arange(1, n + 1, dtype=torch.float64)).to(dev)
     for s in range(0, w.shape[0], chunk):
         W = w[s:s + chunk]
         X = x[s:s + chunk]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            ta = (-h - X) / W
-            tb = (h - X) / W
-            lo = np.where(W == 0, np.where(np.abs(X) < h, -np.inf, np.inf), np.minimum(ta, tb))
-            hi = np.where(W == 0, np.where(np.abs(X) < h, np.inf, -np.inf), np.maximum(ta, tb))
-            t0 = lo.max(1)
-            t1 = hi.min(1)
-            valid = t0 < t1
-            t0 = np.where(valid, t0, 0.0)
-            t1 = np.where(valid, t1, 0.0)
-            T = (knots[None, None, :] - X[:, :, None]) / W[:, :, None]
-        T = np.where(np.isfinite(T), T, t0[:, None, None])
-        T = np.clip(T, t0[:, None, None], t1[:, None, None]).reshape(W.shape[0], -1)
-        T = np.sort(np.concatenate([t0[:, None], T, t1[:, None]], axis=1), axis=1)
+        t0, t1, valid = _chord(n, W, X)
+        t0 = torch.where(valid, t0, torch.zeros_like(t0))
+        t1 = torch.where(valid, t1, torch.zeros_like(t1))
+        T = (knots[None, None, :] - X[:, :, None]) / W[:, :, None]
+        T = torch.where(torch.isfinite(T), T, t0[:, None, None])
+        T = torch.minimum(torch.maximum(T, t0[:, None, None]), t1[:, None, None]).reshape(W.shape[0], -1)
+        T = torch.sort(torch.cat([t0[:, None], T, t1[:, None]], dim=1), dim=1).values
         mid = 0.5 * (T[:, 1:] + T[:, :-1])
         half = 0.5 * (T[:, 1:] - T[:, :-1])
         t = mid[..., None] + half[..., None] * gx                       # [B, S, m]
         pos = X[:, None, None, :] + t[..., None] * W[:, None, None, :]  # [B, S, m, 3]
         val = _bspline(n, pos).prod(-1)
         seg = (val * gw).sum(-1) * half
-        out[s:s + chunk] = np.where(valid, seg.sum(-1), 0.0)
-    return out
+        out[s:s + chunk] = torch.where(valid, seg.sum(-1), torch.zeros_like(t0))
+    return out.numpy() if to_np else out
 
 
 # --------------------------------------------------------------------------
@@ -149,6 +183,13 @@ def make_torch_model(n: int):
     from torch import nn
 
     class FootprintMLP(nn.Module):
+        """``quant`` selects the arithmetic of the hidden layers: "fp32";
+        "split" -- the kernel's: weights rounded to BF16, each activation
+        entering a BF16 layer carried as the sum of two BF16 numbers (its
+        rounding and the rounding of the remainder); "bf16" -- weights and
+        activations each rounded once to BF16.  Rounding is round to nearest
+        even with a straight-through gradient."""
+
         def __init__(self):
             super().__init__()
             sc, sh = feature_scale(n)
@@ -158,19 +199,27 @@ def make_torch_model(n: int):
             self.hidden = nn.ModuleList([nn.Linear(HIDDEN, HIDDEN) for _ in range(DEPTH - 1)])
             self.out = nn.Linear(HIDDEN, 1)
             self.out_scale = 0.5
-            self.quant = False
+            self.quant = "fp32"
 
         @staticmethod
         def _bf16(t):
-            # straight-through rounding to BF16 (round to nearest even)
             return t + (t.to(torch.bfloat16).to(t.dtype) - t).detach()
+
+        def _act(self, a):
+            if self.quant == "bf16":
+                return self._bf16(a)
+            if self.quant == "split":
+                hi = a.to(torch.bfloat16).to(a.dtype)
+                lo = (a - hi).to(torch.bfloat16).to(a.dtype)
+                return a + (hi + lo - a).detach()
+            return a
 
         def forward(self, f):
             z = f * self.in_scale + self.in_shift
             a = torch.nn.functional.silu(self.l1(z))
             for lin in self.hidden:
-                if self.quant:
-                    a = torch.nn.functional.linear(self._bf16(a), self._bf16(lin.weight), lin.bias)
+                if self.quant != "fp32":
+                    a = torch.nn.functional.linear(self._act(a), self._bf16(lin.weight), lin.bias)
                 else:
                     a = lin(a)
                 a = torch.nn.functional.silu(a)
@@ -185,19 +234,19 @@ def model_to_blob(model, n: int, seed: int, rel_fp32: float, rel_bf16: float) ->
     import torch
 
     with torch.no_grad():
-        sc = model.in_scale.double().numpy()
-        sh = model.in_shift.double().numpy()
-        W1 = model.l1.weight.double().numpy()
-        b1 = model.l1.bias.double().numpy()
+        sc = model.in_scale.detach().cpu().double().numpy()
+        sh = model.in_shift.detach().cpu().double().numpy()
+        W1 = model.l1.weight.detach().cpu().double().numpy()
+        b1 = model.l1.bias.detach().cpu().double().numpy()
         W1f = (W1 * sc[None, :]).astype(np.float32)
         b1f = (b1 + W1 @ sh).astype(np.float32)
         parts = [W1f.tobytes(), b1f.tobytes()]
         for lin in model.hidden:
-            wb = lin.weight.detach().float().to(torch.bfloat16).view(torch.int16).numpy().astype(np.int16)
+            wb = lin.weight.detach().cpu().float().to(torch.bfloat16).view(torch.int16).numpy().astype(np.int16)
             parts.append(wb.tobytes())
-            parts.append(lin.bias.detach().float().numpy().astype(np.float32).tobytes())
-        wo = (model.out.weight.double().numpy().reshape(-1) * model.out_scale).astype(np.float32)
-        bo = np.array([model.out.bias.double().item() * model.out_scale], dtype=np.float32)
+            parts.append(lin.bias.detach().cpu().float().numpy().astype(np.float32).tobytes())
+        wo = (model.out.weight.detach().cpu().double().numpy().reshape(-1) * model.out_scale).astype(np.float32)
+        bo = np.array([model.out.bias.detach().cpu().double().item() * model.out_scale], dtype=np.float32)
         parts += [wo.tobytes(), bo.tobytes()]
     header = struct.pack(HEADER_FMT, MAGIC, VERSION, n, IN_DIM, HIDDEN, DEPTH, ACT_SILU, FOLD_ID, seed,
                          float(rel_fp32), float(rel_bf16))
@@ -235,21 +284,32 @@ def parse_blob(blob: bytes) -> dict:
     return d
 
 
-def blob_forward(blob: dict, feats: np.ndarray, bf16_activations: bool = True) -> np.ndarray:
-    """Evaluate a parsed blob on [B, 5] FP32 features with the kernel's
-    precision split (numpy; activations entering the BF16 layers are rounded
-    to BF16 with round-to-nearest-even when ``bf16_activations``)."""
+def to_bf16(a: np.ndarray) -> np.ndarray:
+    """Round FP32 values to BF16 (round to nearest even), returned as FP32."""
+    b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    rnd = ((b >> 16) & 1) + 0x7FFF
+    return ((b + rnd) & 0xFFFF0000).astype(np.uint32).view(np.float32)
+
+
+def blob_forward(blob: dict, feats: np.ndarray, activations: str = "split") -> np.ndarray:
+    """Evaluate a parsed blob on [B, 5] FP32 features (numpy).  The hidden
+    weights are the blob's BF16 values; ``activations`` is how the inputs of
+    the three BF16 layers are carried: "split" (the kernel's: the sum of two
+    BF16 numbers, the rounding of the FP32 value and the rounding of the
+    remainder), "bf16" (one rounding) or "fp32"."""
     def silu(z):
         return z / (1.0 + np.exp(-z))
-
-    def to_bf16(a):
-        b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
-        rnd = ((b >> 16) & 1) + 0x7FFF
-        return ((b + rnd) & 0xFFFF0000).astype(np.uint32).view(np.float32)
 
     f = np.asarray(feats, dtype=np.float32)
     a = silu(f @ blob["W1"].T + blob["b1"]).astype(np.float32)
     for W, b in zip(blob["Wh"], blob["bh"]):
-        inp = to_bf16(a) if bf16_activations else a
-        a = silu(inp.astype(np.float64) @ W.T.astype(np.float64) + b).astype(np.float32)
+        if activations == "split":
+            hi = to_bf16(a)
+            lo = to_bf16((a - hi).astype(np.float32))
+            inp = hi.astype(np.float64) + lo.astype(np.float64)
+        elif activations == "bf16":
+            inp = to_bf16(a).astype(np.float64)
+        else:
+            inp = a.astype(np.float64)
+        a = silu(inp @ W.T.astype(np.float64) + b).astype(np.float32)
     return (a.astype(np.float64) @ blob["Wo"] + blob["bo"]).astype(np.float32)

@@ -43,6 +43,15 @@ def _dev_ptr(t: torch.Tensor, dtype, device, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_shape(t, shape, name: str):
+    """The library receives raw pointers only: every buffer must have exactly
+    the shape the call reads or writes (a smaller one would be overrun)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if tuple(t.shape) != tuple(int(s) for s in shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(int(s) for s in shape)}")
+
+
 class Context:
     """An ss_ctx: degree n in 0..3, form 'quad' (exact FP32) or 'mlp' (BF16 network)."""
 
@@ -78,8 +87,10 @@ class Context:
         if c.dim() != 3:
             raise ValueError("coefficients must be [N3, N2, N1]")
         dims = (c.shape[2], c.shape[1], c.shape[0])
+        shape = (geom.n_views, geom.det_rows, geom.det_cols)
         if out is None:
-            out = torch.empty((geom.n_views, geom.det_rows, geom.det_cols), dtype=torch.float32, device=c.device)
+            out = torch.empty(shape, dtype=torch.float32, device=c.device)
+        _check_shape(out, shape, "out")
         g = _lib.GeometryArg(geom)
         _lib.check(self._lib.ss_project(self._h, _dev_ptr(c, torch.float32, self.device, "c"), _lib.dims_arg(dims),
                                         g.ref(), _dev_ptr(out, torch.float32, self.device, "out"),
@@ -88,10 +99,11 @@ class Context:
 
     def backproject(self, y: torch.Tensor, geom, dims, out: torch.Tensor | None = None) -> torch.Tensor:
         """Transpose of ``project``: coefficients [N3, N2, N1] from y [V, R, C]."""
+        shape = (dims[2], dims[1], dims[0])
         if out is None:
-            out = torch.empty((dims[2], dims[1], dims[0]), dtype=torch.float32, device=y.device)
-        if y.numel() != geom.n_views * geom.det_rows * geom.det_cols:
-            raise ValueError("sinogram size does not match the geometry")
+            out = torch.empty(shape, dtype=torch.float32, device=y.device)
+        _check_shape(y, (geom.n_views, geom.det_rows, geom.det_cols), "y")
+        _check_shape(out, shape, "out")
         g = _lib.GeometryArg(geom)
         _lib.check(self._lib.ss_backproject(self._h, _dev_ptr(y, torch.float32, self.device, "y"), g.ref(),
                                             _lib.dims_arg(dims), _dev_ptr(out, torch.float32, self.device, "out"),
@@ -100,7 +112,10 @@ class Context:
 
     def footprint(self, dirs: torch.Tensor, offsets: torch.Tensor) -> torch.Tensor:
         """P phi(w, x) for pairs (dirs [K, 3] unit, offsets [K, 3])."""
+        if dirs.dim() != 2 or dirs.shape[1] != 3:
+            raise ValueError("dirs must be [K, 3]")
         k = dirs.shape[0]
+        _check_shape(offsets, (k, 3), "offsets")
         out = torch.empty(k, dtype=torch.float32, device=dirs.device)
         _lib.check(self._lib.ss_footprint(self._h, _dev_ptr(dirs, torch.float32, self.device, "dirs"),
                                           _dev_ptr(offsets, torch.float32, self.device, "offsets"), k,
@@ -113,12 +128,17 @@ class Context:
             out = torch.empty((), dtype=torch.float64, device=a.device)
         if a.numel() != b.numel():
             raise ValueError("dot of vectors of different lengths")
+        if out.numel() != 1:
+            raise ValueError("out must hold one FP64 value")
         _lib.check(self._lib.ss_dot_f64(self._h, _dev_ptr(a, torch.float32, self.device, "a"),
                                         _dev_ptr(b, torch.float32, self.device, "b"), a.numel(),
                                         _dev_ptr(out, torch.float64, self.device, "out"), _stream(self.device)))
         return out
 
     def ratio(self, num: torch.Tensor, den: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        for t, name in ((num, "num"), (den, "den"), (out, "out")):
+            if t.numel() != 1:
+                raise ValueError(f"{name} must hold one FP64 value")
         _lib.check(self._lib.ss_cgls_scalars(self._h, _dev_ptr(num, torch.float64, self.device, "num"),
                                              _dev_ptr(den, torch.float64, self.device, "den"),
                                              _dev_ptr(out, torch.float64, self.device, "out"), _stream(self.device)))
@@ -127,6 +147,8 @@ class Context:
     def axpy(self, alpha: torch.Tensor, sign: int, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         if x.numel() != y.numel():
             raise ValueError("axpy of vectors of different lengths")
+        if alpha.numel() != 1:
+            raise ValueError("alpha must hold one FP64 value")
         _lib.check(self._lib.ss_axpy(self._h, _dev_ptr(alpha, torch.float64, self.device, "alpha"), int(sign),
                                      _dev_ptr(x, torch.float32, self.device, "x"),
                                      _dev_ptr(y, torch.float32, self.device, "y"), x.numel(), _stream(self.device)))
@@ -135,6 +157,8 @@ class Context:
     def xpay(self, beta: torch.Tensor, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         if x.numel() != y.numel():
             raise ValueError("xpay of vectors of different lengths")
+        if beta.numel() != 1:
+            raise ValueError("beta must hold one FP64 value")
         _lib.check(self._lib.ss_xpay(self._h, _dev_ptr(beta, torch.float64, self.device, "beta"),
                                      _dev_ptr(x, torch.float32, self.device, "x"),
                                      _dev_ptr(y, torch.float32, self.device, "y"), x.numel(), _stream(self.device)))

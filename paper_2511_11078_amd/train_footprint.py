@@ -7,7 +7,9 @@ the MLP with Adam on the squared error until a validation error falls below
 a tolerance.  This script follows those steps with these choices:
 
 * labels: exact FP64 footprints (``footprint_net.exact_footprint``) instead
-  of a projector applied to a finely sampled basis;
+  of a projector applied to a finely sampled basis, drawn afresh for every
+  few hundred steps (on the GPU when one is given, where they cost far less
+  than the step itself);
 * offsets: uniform in the disk of radius h*sqrt(3) (circumradius of the
   support cube) of the plane, keeping the samples whose line meets the
   support -- the kernel gates the network by that same test, so samples
@@ -15,17 +17,22 @@ a tolerance.  This script follows those steps with these choices:
 * directions: 70% uniform on the sphere, 30% within 15 degrees of the
   x1-x2 plane (circular and cone-beam trajectories live there);
 * inputs folded into 0 <= w1 <= w2 <= w3 (fold convention 1);
-* Adam, cosine learning-rate decay, fresh samples each step from a
-  regenerated pool, then a short quantisation-aware phase that rounds the
-  hidden weights and the activations entering them to BF16;
+* phase 1: Adam with a short warm-up and cosine decay of the learning rate,
+  FP32 arithmetic;
+* phase 2: the kernel's arithmetic (hidden weights rounded to BF16 with a
+  straight-through gradient, activations carried as two BF16 numbers), Adam
+  at a small, decaying learning rate;
+* phase 3: the hidden weights frozen at their BF16 values, the FP32
+  parameters (layer 1, every bias, the output layer) refitted by L-BFGS on a
+  large fixed sample;
 * stopping: a fixed step budget; the reached validation relative L2 error
-  (FP32 and BF16-quantised) is written into the blob header.
+  (FP32, and in the kernel's arithmetic) is written into the blob header.
 
-Usage:  python -m paper_2511_11078_amd.train_footprint --degree 3 --out weights/mlp_n3.bin
+A run can be cut into pieces (``--time-limit`` seconds each): the state is
+kept in ``--ckpt`` and the next call with the same arguments resumes it.
 
-The shipped degree-3 and degree-2 weights used --steps 80000 --qat-steps 8000
---batch 32768 --lr 2e-3 --threads 6 --pool 2000000 (about 60-70 minutes each
-on 6 host cores).
+Usage:  python -m paper_2511_11078_amd.train_footprint --degree 3 --device cuda \\
+            --ckpt train_n3.pt --out paper_2511_11078_amd/weights/mlp_n3.bin
 """
 from __future__ import annotations
 
@@ -39,115 +46,210 @@ import numpy as np
 from . import footprint_net as fn
 
 
-def sample_pairs(n: int, count: int, rng) -> tuple[np.ndarray, np.ndarray]:
-    """Directions and offsets (lines meeting the support), FP64."""
+def sample_pairs_t(n: int, count: int, gen, device="cpu"):
+    """Directions and offsets (lines meeting the support), FP64 torch
+    tensors on ``device``, drawn with the torch generator ``gen``."""
+    import torch
+
     h = 0.5 * (n + 1)
     r_s = h * math.sqrt(3.0)
+    f64 = dict(dtype=torch.float64, device=device)
     ws, xs = [], []
     have = 0
     while have < count:
         m = 2 * (count - have) + 1024
-        w = rng.standard_normal((m, 3))
-        low = rng.random(m) < 0.3
-        w[low, 2] = np.tan(np.deg2rad(rng.uniform(-15.0, 15.0, low.sum()))) * np.linalg.norm(w[low, :2], axis=1)
-        w /= np.linalg.norm(w, axis=1, keepdims=True)
+        w = torch.randn(m, 3, generator=gen, **f64)
+        low = torch.rand(m, generator=gen, **f64) < 0.3
+        ang = torch.deg2rad((torch.rand(m, generator=gen, **f64) * 2.0 - 1.0) * 15.0)
+        w[:, 2] = torch.where(low, torch.tan(ang) * torch.linalg.norm(w[:, :2], dim=1), w[:, 2])
+        w = w / torch.linalg.norm(w, dim=1, keepdim=True)
         # uniform point of the disk of radius r_s in w's perpendicular plane
-        a = rng.standard_normal((m, 3))
-        a -= (a * w).sum(1, keepdims=True) * w
-        a /= np.linalg.norm(a, axis=1, keepdims=True)
-        rad = r_s * np.sqrt(rng.random(m))
+        a = torch.randn(m, 3, generator=gen, **f64)
+        a = a - (a * w).sum(1, keepdim=True) * w
+        a = a / torch.linalg.norm(a, dim=1, keepdim=True)
+        rad = r_s * torch.sqrt(torch.rand(m, generator=gen, **f64))
         x = a * rad[:, None]
         keep = fn.chord_nonempty(n, w, x)
         ws.append(w[keep])
         xs.append(x[keep])
         have += int(keep.sum())
-    return np.concatenate(ws)[:count], np.concatenate(xs)[:count]
+    return torch.cat(ws)[:count], torch.cat(xs)[:count]
 
 
-def make_dataset(n: int, count: int, seed: int):
-    rng = np.random.default_rng(seed)
-    w, x = sample_pairs(n, count, rng)
-    y = fn.exact_footprint(n, w, x)
-    f = fn.fold_features(w, x)
-    return f.astype(np.float32), y.astype(np.float32)
-
-
-def rel_l2(model, f, y, quant: bool, chunk: int = 1 << 16) -> float:
+def sample_pairs(n: int, count: int, rng) -> tuple[np.ndarray, np.ndarray]:
+    """numpy form of ``sample_pairs_t`` on the host, seeded from ``rng``."""
     import torch
 
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(int(rng.integers(0, 2 ** 62)))
+    w, x = sample_pairs_t(n, count, gen)
+    return w.numpy(), x.numpy()
+
+
+def make_dataset(n: int, count: int, seed: int, device="cpu"):
+    """FP32 features and FP32 labels (FP64 exact footprints rounded once)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    w, x = sample_pairs_t(n, count, gen, device)
+    y = fn.exact_footprint(n, w, x, chunk=1 << 20)
+    f = fn.fold_features(w, x)
+    return f.to(torch.float32), y.to(torch.float32)
+
+
+def rel_l2(model, f, y, quant: str, chunk: int = 1 << 18) -> float:
+    import torch
+
+    prev = model.quant
     model.quant = quant
     num = den = 0.0
     with torch.no_grad():
         for s in range(0, f.shape[0], chunk):
-            p = model(torch.from_numpy(f[s:s + chunk])).double().numpy()
-            t = y[s:s + chunk].astype(np.float64)
-            num += ((p - t) ** 2).sum()
-            den += (t ** 2).sum()
-    model.quant = False
+            p = model(f[s:s + chunk]).double()
+            t = y[s:s + chunk].double()
+            num += float(((p - t) ** 2).sum())
+            den += float((t ** 2).sum())
+    model.quant = prev
     return math.sqrt(num / den)
 
 
-def train(n: int, steps: int, qat_steps: int, batch: int, lr: float, seed: int, out: str,
-          threads: int, pool: int, log=print):
+def lr_at(step: int, steps: int, qat_steps: int, lr: float, warmup: int = 2000) -> float:
+    if step < steps:
+        if step < warmup:
+            return lr * (step + 1) / warmup
+        p = (step - warmup) / max(steps - warmup, 1)
+        return 1e-7 + (lr - 1e-7) * 0.5 * (1 + math.cos(math.pi * p))
+    p = (step - steps) / max(qat_steps, 1)
+    return 1e-8 + (0.03 * lr) * 0.5 * (1 + math.cos(math.pi * p))
+
+
+def refit_fp32_params(model, f, y, iters: int, log):
+    """Freeze the hidden weights at their BF16 values and refit the FP32
+    parameters (layer 1, biases, output layer) by full-batch L-BFGS in the
+    kernel's arithmetic."""
+    import torch
+
+    with torch.no_grad():
+        for lin in model.hidden:
+            lin.weight.copy_(lin.weight.to(torch.bfloat16).to(torch.float32))
+            lin.weight.requires_grad_(False)
+    params = [model.l1.weight, model.l1.bias, model.out.weight, model.out.bias] + [l.bias for l in model.hidden]
+    model.quant = "split"
+    opt = torch.optim.LBFGS(params, lr=1.0, max_iter=iters, history_size=50, tolerance_grad=0.0,
+                            tolerance_change=0.0, line_search_fn="strong_wolfe")
+    chunk = 1 << 20
+    scale = 1.0 / float((y.double() ** 2).mean())
+
+    def closure():
+        opt.zero_grad(set_to_none=True)
+        total = 0.0
+        for s in range(0, f.shape[0], chunk):
+            p = model(f[s:s + chunk])
+            loss = ((p - y[s:s + chunk]) ** 2).sum() * (scale / f.shape[0])
+            loss.backward()
+            total += float(loss.detach())
+        return torch.tensor(total)
+
+    loss = opt.step(closure)
+    log(f"refit: {iters} L-BFGS iterations, relative loss {float(loss):.3e}")
+    for lin in model.hidden:
+        lin.weight.requires_grad_(True)
+
+
+def train(n: int, steps: int, qat_steps: int, batch: int, lr: float, seed: int, out: str, threads: int,
+          pool: int, device: str, ckpt: str | None, time_limit: float, refit_iters: int, refit_samples: int,
+          log=print):
     import torch
 
     torch.set_num_threads(threads)
     torch.manual_seed(seed)
-    model = fn.make_torch_model(n)
-    fval, yval = make_dataset(n, 200_000, seed + 1000)
+    dev = torch.device(device)
+    model = fn.make_torch_model(n).to(dev)
     opt = torch.optim.Adam(model.parameters(), lr=lr)
+    start = 0
+    if ckpt and os.path.exists(ckpt):
+        st = torch.load(ckpt, map_location=dev, weights_only=True)
+        model.load_state_dict(st["model"])
+        opt.load_state_dict(st["opt"])
+        start = int(st["step"])
+        log(f"resumed from {ckpt} at step {start}")
+    fval, yval = make_dataset(n, 1_000_000, seed + 1000, dev)
     total = steps + qat_steps
     t0 = time.time()
+    last_log = 0.0
+    pool_every = max(1, pool // batch)
+    gen = torch.Generator(device=dev)
+    step = start
     fpool = ypool = None
-    for step in range(total):
-        if step % 2000 == 0:
-            fpool, ypool = make_dataset(n, pool, seed + step)
-            fpool_t = torch.from_numpy(fpool)
-            ypool_t = torch.from_numpy(ypool)
-        if step < steps:
-            cur = lr * (0.01 + 0.99 * 0.5 * (1 + math.cos(math.pi * step / steps)))
-        else:
-            model.quant = True
-            cur = lr * 0.02 * (1 - (step - steps) / max(qat_steps, 1)) + 1e-6
+    while step < total:
+        if fpool is None or (step - start) % pool_every == 0:
+            fpool, ypool = make_dataset(n, pool, seed + 7919 * step + 1, dev)
+            gen.manual_seed(seed + step)
+        model.quant = "split" if step >= steps else "fp32"
+        cur = lr_at(step, steps, qat_steps, lr)
         for g in opt.param_groups:
             g["lr"] = cur
-        idx = torch.randint(0, fpool.shape[0], (batch,))
-        pred = model(fpool_t[idx])
-        loss = torch.mean((pred - ypool_t[idx]) ** 2)
+        idx = torch.randint(0, fpool.shape[0], (batch,), generator=gen, device=dev)
+        pred = model(fpool[idx])
+        loss = torch.mean((pred - ypool[idx]) ** 2)
         opt.zero_grad(set_to_none=True)
         loss.backward()
         opt.step()
-        if step % 1000 == 0 or step == total - 1:
-            r32 = rel_l2(model, fval, yval, False)
-            rq = rel_l2(model, fval, yval, True)
-            model.quant = step >= steps
-            log(f"step {step:6d} lr {cur:.2e} loss {loss.item():.3e} val_rel_fp32 {r32:.3e} "
-                f"val_rel_bf16 {rq:.3e} t {time.time() - t0:.0f}s")
-    model.quant = False
-    r32 = rel_l2(model, fval, yval, False)
-    rq = rel_l2(model, fval, yval, True)
+        step += 1
+        now = time.time() - t0
+        if step % 10000 == 0 or step == total or now - last_log > 45.0:
+            last_log = now
+            r32 = rel_l2(model, fval, yval, "fp32")
+            rq = rel_l2(model, fval, yval, "split")
+            log(f"step {step:7d}/{total} lr {cur:.2e} loss {loss.item():.3e} val_rel_fp32 {r32:.3e} "
+                f"val_rel_kernel {rq:.3e} t {now:.0f}s")
+        if ckpt and (now > time_limit or step == total):
+            torch.save({"model": model.state_dict(), "opt": opt.state_dict(), "step": step}, ckpt)
+            if step < total:
+                log(f"time limit: state saved to {ckpt} at step {step}")
+                return None
+    if refit_iters > 0:
+        fr, yr = make_dataset(n, refit_samples, seed + 2000, dev)
+        before = rel_l2(model, fval, yval, "split")
+        saved = {k: v.clone() for k, v in model.state_dict().items()}
+        refit_fp32_params(model, fr, yr, refit_iters, log)
+        after = rel_l2(model, fval, yval, "split")
+        log(f"refit: validation rel-L2 in the kernel's arithmetic {before:.3e} -> {after:.3e}")
+        if not after < before:
+            model.load_state_dict(saved)
+    model.quant = "fp32"
+    r32 = rel_l2(model, fval, yval, "fp32")
+    rq = rel_l2(model, fval, yval, "split")
+    r1 = rel_l2(model, fval, yval, "bf16")
     blob = fn.model_to_blob(model, n, seed, r32, rq)
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     with open(out, "wb") as fh:
         fh.write(blob)
-    log(f"wrote {out}: val rel-L2 fp32 {r32:.3e} bf16 {rq:.3e}")
+    log(f"wrote {out}: val rel-L2 fp32 {r32:.3e}, kernel arithmetic {rq:.3e} "
+        f"(activations rounded once to BF16: {r1:.3e})")
     return model
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--degree", type=int, default=3)
-    ap.add_argument("--steps", type=int, default=40000)
-    ap.add_argument("--qat-steps", type=int, default=6000)
-    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--steps", type=int, default=300000)
+    ap.add_argument("--qat-steps", type=int, default=40000)
+    ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--threads", type=int, default=6)
-    ap.add_argument("--pool", type=int, default=1_000_000)
+    ap.add_argument("--threads", type=int, default=8)
+    ap.add_argument("--pool", type=int, default=4_000_000)
+    ap.add_argument("--device", default="cpu")
+    ap.add_argument("--ckpt", default=None, help="state file for runs cut into pieces")
+    ap.add_argument("--time-limit", type=float, default=float("inf"), help="seconds before saving and stopping")
+    ap.add_argument("--refit-iters", type=int, default=500)
+    ap.add_argument("--refit-samples", type=int, default=4_000_000)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    train(a.degree, a.steps, a.qat_steps, a.batch, a.lr, a.seed, a.out, a.threads, a.pool,
-          log=lambda s: print(s, flush=True))
+    train(a.degree, a.steps, a.qat_steps, a.batch, a.lr, a.seed, a.out, a.threads, a.pool, a.device, a.ckpt,
+          a.time_limit, a.refit_iters, a.refit_samples, log=lambda s: print(s, flush=True))
 
 
 if __name__ == "__main__":

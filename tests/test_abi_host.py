@@ -121,3 +121,30 @@ def test_device_gauss_legendre_constants():
         xr, wr = np.polynomial.legendre.leggauss(m)
         np.testing.assert_allclose(xs, sorted(set(np.round(np.abs(xr), 15))), atol=1e-15)
         np.testing.assert_allclose(ws, sorted(set(np.round(wr, 15))), atol=1e-15)
+
+
+def test_binding_rejects_wrongly_sized_buffers():
+    """The binding checks every buffer's shape before the library sees its
+    pointer (no GPU: the check comes before any device access)."""
+    import torch
+
+    from paper_2511_11078_amd.ops import Context
+
+    ctx = object.__new__(Context)  # no device context needed for argument checks
+    ctx.device, ctx._h, ctx._lib = 0, None, None
+    g = synth.parallel_geometry(synth.fibonacci_directions(3), 4, 5)
+    c = torch.zeros(6, 5, 4)
+    with pytest.raises(ValueError):
+        ctx.project(c, g, out=torch.zeros(3, 4, 4))
+    with pytest.raises(ValueError):
+        ctx.project(c, g, out=torch.zeros(3 * 4 * 5))
+    with pytest.raises(ValueError):
+        ctx.backproject(torch.zeros(3, 4, 5), g, (4, 5, 6), out=torch.zeros(6, 5, 3))
+    with pytest.raises(ValueError):
+        ctx.backproject(torch.zeros(3, 5, 4), g, (4, 5, 6), out=torch.zeros(6, 5, 4))
+    with pytest.raises(ValueError):
+        ctx.footprint(torch.zeros(8, 3), torch.zeros(7, 3))
+    with pytest.raises(ValueError):
+        ctx.dot_f64(torch.zeros(4), torch.zeros(4), out=torch.zeros(2, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        ctx.axpy(torch.zeros(2, dtype=torch.float64), 1, torch.zeros(4), torch.zeros(4))
