@@ -16,7 +16,9 @@
  * (projection algorithm and neighbour search of Sec. 2.3).  The footprint
  * P phi(w, x) = int phi(x + t w) dt is evaluated either
  *   - exactly, by piecewise Gauss-Legendre quadrature in FP32
- *     (SS_FORM_QUAD_FP32), or
+ *     (SS_FORM_QUAD_FP32: integrated knot cell by knot cell along each line,
+ *     the nodes of a cell shared by the bases covering it; or
+ *     SS_FORM_QUAD_PAIR_FP32: per (line, basis) pair on the network's walk), or
  *   - by the learned network f_theta of Sec. 2.2 (SS_FORM_MLP_BF16):
  *     5 -> 4 x 64 (SiLU) -> 1, hidden layers on BF16 matrix cores with FP32
  *     accumulation, gated by the exact line/support intersection test.
@@ -69,8 +71,13 @@ typedef enum {
 } ss_status;
 
 typedef enum {
-    SS_FORM_QUAD_FP32 = 0, /* exact piecewise Gauss-Legendre footprint, FP32 */
-    SS_FORM_MLP_BF16 = 1   /* learned footprint, BF16 MFMA + FP32 accumulate */
+    SS_FORM_QUAD_FP32 = 0,      /* exact piecewise Gauss-Legendre footprint, FP32 */
+    SS_FORM_MLP_BF16 = 1,       /* learned footprint, BF16 MFMA + FP32 accumulate */
+    SS_FORM_QUAD_PAIR_FP32 = 2  /* the exact FP32 footprint evaluated per (line, basis)
+                                   pair on the traversal of SS_FORM_MLP_BF16: the same
+                                   slab windows (forward) and coefficient-brick gather
+                                   (adjoint), only the footprint differs -- the
+                                   reference point for the network's speed (Sec. 2.2) */
 } ss_form;
 
 typedef enum {
@@ -98,14 +105,15 @@ typedef struct ss_ctx ss_ctx;
  * (0..3) and footprint form `form`.  For SS_FORM_MLP_BF16, `mlp_blob` /
  * `blob_bytes` is a host copy of the trained network (layout below); the
  * weights are uploaded once and owned by the context.  For
- * SS_FORM_QUAD_FP32 pass NULL, 0.
+ * SS_FORM_QUAD_FP32 and SS_FORM_QUAD_PAIR_FP32 pass NULL, 0.
  * Blob layout (little endian): char magic[8] = "SSMLP\0\0\1"; uint32
  * version (1), degree, in (5), hidden (64), depth (4), activation (1 = SiLU),
  * fold convention (1), training seed; float rel_l2_fp32, rel_l2_bf16; then
  * W1[64][5] f32, b1[64] f32, 3 x (W[64][64] bf16 row-major [out][in],
  * b[64] f32), Wout[64] f32, bout f32.
- * Errors: SS_EINVAL (out == NULL, bad degree/form), SS_EUNSUPPORTED
- * (MLP form with degree 0), SS_EBLOB, SS_EDEVICE, SS_ENOMEM. */
+ * Errors: SS_EINVAL (out == NULL, bad degree/form, a blob given to an exact
+ * form), SS_EUNSUPPORTED (MLP form with degree 0), SS_EBLOB, SS_EDEVICE,
+ * SS_ENOMEM. */
 ss_status ss_create(ss_ctx **out, int device, int degree, ss_form form,
                     const void *mlp_blob, size_t blob_bytes);
 

@@ -62,12 +62,15 @@ def _load():
     geo = [I, I, I, I, P]
     lib.or_make_rays.argtypes = [I, I, I, I, P, P, L, P, P]
     lib.or_project.argtypes = [I, P, P] + geo + [P, L, P]
+    lib.or_project_lines.argtypes = [I, P, P, L, P, P, P]
     lib.or_project_basis_sum.argtypes = [I, P, P] + geo + [P, L, P]
     lib.or_counts.argtypes = [I, P] + geo + [P, L, P, P]
     lib.or_direct_counts.argtypes = [I, P] + geo + [P, L, P]
     lib.or_backproject_subset.argtypes = [I, P, P] + geo + [P, L, P]
     lib.or_dense_matrix.argtypes = [I, P] + geo + [P, L, P]
     lib.or_num_threads.restype = I
+    lib.or_set_num_threads.argtypes = [I]
+    lib.or_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -99,6 +102,11 @@ def _idx(idx, total):
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the following oracle calls (k < 1: back to the default)."""
+    _load().or_set_num_threads(int(k))
 
 
 def bspline(n: int, x, truncated_power: bool = False) -> np.ndarray:
@@ -163,6 +171,19 @@ def project(c, geom, n: int = 3, rays=None) -> np.ndarray:
     if rc:
         raise ValueError("oracle project failed")
     return out if rays is not None else out.reshape(g[1], g[2], g[3])
+
+
+def project_lines(c, a, w, n: int = 3) -> np.ndarray:
+    """O3 on explicit lines: y_k = int f(a_k + t w_k) dt (eq. (2)) for FP64
+    anchors a [K, 3] and unit directions w [K, 3]."""
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float32))
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, 3))
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1, 3))
+    out = np.empty(a.shape[0])
+    N = _dims(c.shape[::-1])
+    if _load().or_project_lines(n, _ptr(c), _ptr(N), a.shape[0], _ptr(a), _ptr(w), _ptr(out)):
+        raise ValueError("bad degree or size")
+    return out
 
 
 def project_basis_sum(c, geom, n: int = 3, rays=None) -> np.ndarray:

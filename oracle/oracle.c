@@ -424,6 +424,25 @@ int or_project(int n, const float *c, const int64_t N[3], int kind, int V, int R
     return bad;
 }
 
+/* O3 on explicitly given lines a_k + t w_k (w_k unit): the same direct     */
+/* integral as or_project, for lines that do not come from a geometry.      */
+int or_project_lines(int n, const float *c, const int64_t N[3], int64_t nlines, const double *a,
+                     const double *w, double *out)
+{
+    if (n < 0 || n > 3) return 1;
+    for (int i = 0; i < 3; ++i)
+        if (N[i] < 1) return 1;
+    int64_t cap = 2 + 3 * (N[0] + N[1] + N[2]) + 32;
+#pragma omp parallel
+    {
+        double *T = (double *)malloc(sizeof(double) * cap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t k = 0; k < nlines; ++k) out[k] = ray_direct(n, c, N, a + 3 * k, w + 3 * k, T);
+        free(T);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Enumerate every basis q in the index box whose open support meets the    */
 /* ray, by nested clipping of the ray's parameter interval axis by axis     */
@@ -728,5 +747,18 @@ int or_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Number of OpenMP threads of the following calls (timing of the oracle on
+ * one core and on all of them); k < 1 restores the default. */
+void or_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    static int deflt = 0;
+    if (deflt == 0) deflt = omp_get_max_threads();
+    omp_set_num_threads(k >= 1 ? k : deflt);
+#else
+    (void)k;
 #endif
 }

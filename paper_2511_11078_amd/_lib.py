@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsplinesplat.so")
 
 SS_OK, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EUNSUPPORTED, SS_EBLOB = range(6)
-FORMS = {"quad": 0, "mlp": 1}
+FORMS = {"quad": 0, "mlp": 1, "pair": 2}
 KINDS = {"parallel": 0, "cone": 1}
 STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_EDEVICE", 4: "SS_EUNSUPPORTED",
                 5: "SS_EBLOB"}

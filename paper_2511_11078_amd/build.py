@@ -21,7 +21,6 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsplinesplat.so")
-PROBE = os.path.join(HERE, "peaks_probe")
 SOURCES = ["ss_abi.cpp", "ss_kernels.hip", "ss_mlp.hip"]
 ARCH = "gfx950"
 
@@ -66,11 +65,6 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    # the peak-rate probe (a measurement aid, not part of the library)
-    cmd = [cc, "-x", "hip", *common_flags(), os.path.join(CSRC, "peaks_probe.hip"), "-o", PROBE]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on peaks_probe.hip:\n{r.stdout}\n{r.stderr}")
     return LIB
 
 

@@ -222,11 +222,12 @@ ss_status ss_create(ss_ctx **out, int device, int degree, ss_form form, const vo
     if (!out) return fail(SS_EINVAL, "out is NULL");
     *out = nullptr;
     if (degree < 0 || degree > 3) return fail(SS_EINVAL, "degree %d outside 0..3", degree);
-    if (form != SS_FORM_QUAD_FP32 && form != SS_FORM_MLP_BF16) return fail(SS_EINVAL, "unknown form %d", (int)form);
+    if (form != SS_FORM_QUAD_FP32 && form != SS_FORM_MLP_BF16 && form != SS_FORM_QUAD_PAIR_FP32)
+        return fail(SS_EINVAL, "unknown form %d", (int)form);
     if (form == SS_FORM_MLP_BF16 && degree == 0)
         return fail(SS_EUNSUPPORTED, "the network form is built for degrees 1..3");
-    if (form == SS_FORM_QUAD_FP32 && (mlp_blob || blob_bytes))
-        return fail(SS_EINVAL, "the quadrature form takes no weight blob");
+    if (form != SS_FORM_MLP_BF16 && (mlp_blob || blob_bytes))
+        return fail(SS_EINVAL, "the exact footprint forms take no weight blob");
     std::vector<unsigned char> image;
     if (form == SS_FORM_MLP_BF16) {
         if (!mlp_blob) return fail(SS_EBLOB, "the network form needs a weight blob");
@@ -312,8 +313,9 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
             a.scratch = ctx->d_cells;
             a.scratch_floats = ctx->cells_cap;
         }
-        e = ctx->form == SS_FORM_QUAD_FP32 ? ss::launch_project_quad(ctx->degree, a, st)
-                                           : ss::launch_project_mlp(ctx->degree, a, st);
+        e = ctx->form == SS_FORM_QUAD_FP32   ? ss::launch_project_quad(ctx->degree, a, st)
+            : ctx->form == SS_FORM_MLP_BF16  ? ss::launch_project_mlp(ctx->degree, a, st)
+                                             : ss::launch_project_pair(ctx->degree, a, st);
     } else {
         a.sino_in = in;
         a.coeffs_out = out;
@@ -322,8 +324,9 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
             a.scratch = ctx->d_cells;
             a.scratch_floats = ctx->cells_cap;
         }
-        e = ctx->form == SS_FORM_QUAD_FP32 ? ss::launch_backproject_quad(ctx->degree, a, st)
-                                           : ss::launch_backproject_mlp(ctx->degree, a, st);
+        e = ctx->form == SS_FORM_QUAD_FP32   ? ss::launch_backproject_quad(ctx->degree, a, st)
+            : ctx->form == SS_FORM_MLP_BF16  ? ss::launch_backproject_mlp(ctx->degree, a, st)
+                                             : ss::launch_backproject_pair(ctx->degree, a, st);
     }
     if (e != hipSuccess) return hip_fail(e, forward ? "project launch" : "backproject launch");
     return SS_OK;
@@ -348,9 +351,9 @@ ss_status ss_footprint(ss_ctx *ctx, const float *d_dirs, const float *d_offsets,
     DeviceGuard guard(ctx->device);
     if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
     hipStream_t st = (hipStream_t)hip_stream;
-    hipError_t e = ctx->form == SS_FORM_QUAD_FP32
-                       ? ss::launch_footprint_quad(ctx->degree, d_dirs, d_offsets, (int)count, d_out, st)
-                       : ss::launch_footprint_mlp(ctx->degree, ctx->d_mlp, d_dirs, d_offsets, (int)count, d_out, st);
+    hipError_t e = ctx->form == SS_FORM_MLP_BF16
+                       ? ss::launch_footprint_mlp(ctx->degree, ctx->d_mlp, d_dirs, d_offsets, (int)count, d_out, st)
+                       : ss::launch_footprint_quad(ctx->degree, d_dirs, d_offsets, (int)count, d_out, st);
     if (e != hipSuccess) return hip_fail(e, "footprint launch");
     return SS_OK;
 }

@@ -258,6 +258,8 @@ __device__ __forceinline__ void fill_cellray(CellRay &rec, const float *__restri
 // relative to the brick centre).  A line parallel to a knot plane belongs to
 // the cell above it when it lies in the plane (the forward walk's choice);
 // for degree 0 the support is open and such a line meets neither cell.
+// Written without branches (selects only), so that the record is read in
+// one go and the lanes of a wave never split on the rare parallel axis.
 template <int n>
 __device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], float &t0, float &t1) {
     bool in = true;
@@ -265,15 +267,14 @@ __device__ __forceinline__ bool cell_chord(const CellRay &r, const float lo[3], 
     t1 = 3.0e38f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (r.iw[k] == 0.0f) {
-            in = in && (n == 0 ? lo[k] < r.a[k] : lo[k] <= r.a[k]) && r.a[k] < lo[k] + 1.0f;
-        } else {
-            const float ta = (lo[k] - r.a[k]) * r.iw[k], tb = (lo[k] + 1.0f - r.a[k]) * r.iw[k];
-            t0 = fmaxf(t0, fminf(ta, tb));
-            t1 = fminf(t1, fmaxf(ta, tb));
-        }
+        const bool par = r.iw[k] == 0.0f;
+        const bool inside = (n == 0 ? lo[k] < r.a[k] : lo[k] <= r.a[k]) & (r.a[k] < lo[k] + 1.0f);
+        const float ta = (lo[k] - r.a[k]) * r.iw[k], tb = (lo[k] + 1.0f - r.a[k]) * r.iw[k];
+        in = in & (inside | !par);
+        t0 = par ? t0 : fmaxf(t0, fminf(ta, tb));
+        t1 = par ? t1 : fminf(t1, fmaxf(ta, tb));
     }
-    return in && t0 < t1;
+    return in & (t0 < t1);
 }
 
 // Add one line's chord through the cell to the cell's moments: at the m

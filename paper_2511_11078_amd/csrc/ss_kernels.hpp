@@ -54,6 +54,9 @@ hipError_t launch_footprint_quad(int degree, const float *dirs, const float *off
 
 hipError_t launch_project_mlp(int degree, const LaunchArgs &a, hipStream_t st);
 hipError_t launch_backproject_mlp(int degree, const LaunchArgs &a, hipStream_t st);
+// Exact footprint per (line, basis) pair on the network form's walk and gather.
+hipError_t launch_project_pair(int degree, const LaunchArgs &a, hipStream_t st);
+hipError_t launch_backproject_pair(int degree, const LaunchArgs &a, hipStream_t st);
 hipError_t launch_footprint_mlp(int degree, const void *mlp, const float *dirs, const float *offs, int count,
                                 float *out, hipStream_t st);
 // Record a thread-local error message (printf format) and return s.

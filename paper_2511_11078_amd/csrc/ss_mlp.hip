@@ -208,6 +208,7 @@ __device__ __forceinline__ float mlp_wave(const MlpImage &W, const float f[5]) {
     // the two tiles are independent: the scheduler interleaves one tile's
     // matrix-core work with the other's SiLU
     const float ra = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 0);
+    __builtin_amdgcn_sched_barrier(0);
     const float rb = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 32);
     return lane < 32 ? ra : rb;
 }
@@ -332,19 +333,16 @@ __device__ __forceinline__ void walk_init(Walk<n> &W, const LineD &L, const int 
     if (W.j <= W.j1) W.window();
 }
 
-// two workgroups (eight waves) per CU: one wave's matrix-core layers overlap
-// another's SiLU
-template <int n>
-__global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__restrict__ c, int N0, int N1, int N2,
-                                                          const float *__restrict__ geom, int kind, int V, int R,
-                                                          int C, const MlpImage *__restrict__ img,
-                                                          float *__restrict__ y) {
-    __shared__ MlpImage Wt;
-    const int tR = (R + 15) / 16, tC = (C + 15) / 16;
-    int v, tr, tc;
-    if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot: the whole block
-    load_image(Wt, img);
-    __syncthreads();
+// The slab walk of one line per lane, with the footprint of each (line,
+// basis) pair it yields taken from the network (EXACT = false: the wave
+// evaluates the 64 pairs of a round on the matrix cores) or from the exact
+// piecewise Gauss-Legendre integral (EXACT = true: each lane on its own).
+// The exact variant is the reference point of the network: the same walk,
+// windows and pair gating, only the footprint differs.
+template <int n, bool EXACT>
+__device__ __forceinline__ void project_walk(const float *__restrict__ c, int N0, int N1, int N2,
+                                             const float *__restrict__ geom, int kind, int V, int R, int C,
+                                             const MlpImage *Wt, float *__restrict__ y, int v, int tr, int tc) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = tr * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int i = tc * 16 + (wave & 1) * 8 + (lane & 7);
@@ -358,11 +356,13 @@ __global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__rest
     int d = 0, i1 = 1, i2 = 2;
     Fold F;
     Slopes S;
+    float inv_wd = 0.0f;
     bool live = false;
     if (L.ok) {
         walk_init<n>(Wk, L, N, d, i1, i2);
         F = make_fold(L.w);
         S = make_slopes((float)Wk.r1, (float)Wk.r2);
+        inv_wd = (float)(1.0 / fabs(pick3(L.w, d)));
         live = !Wk.done();
     } else {
         F = Fold{};
@@ -388,16 +388,47 @@ __global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__rest
             live = !Wk.done();
         }
         if (__ballot(have) == 0) break;
-        float f[5];
-        f[0] = F.wf[0];
-        f[1] = F.wf[1];
-        f[2] = F.wf[2];
-        f[3] = fmaf(Ui1, u1, Ui2 * u2);
-        f[4] = fmaf(Vi1, u1, Vi2 * u2);
-        const float fp = mlp_wave(Wt, f);
+        float fp;
+        if constexpr (EXACT) {
+            fp = have ? footprint_slab<n>(S, u1, u2) * inv_wd : 0.0f;
+        } else {
+            float f[5];
+            f[0] = F.wf[0];
+            f[1] = F.wf[1];
+            f[2] = F.wf[2];
+            f[3] = fmaf(Ui1, u1, Ui2 * u2);
+            f[4] = fmaf(Vi1, u1, Vi2 * u2);
+            fp = mlp_wave(*Wt, f);
+        }
         if (have) acc = fmaf(c[idx], fp, acc);
     }
     if (pix) y[((int64_t)v * R + j) * C + i] = acc;
+}
+
+// two workgroups (eight waves) per CU: one wave's matrix-core layers overlap
+// another's SiLU
+template <int n>
+__global__ void __launch_bounds__(256, 2) project_mlp_kernel(const float *__restrict__ c, int N0, int N1, int N2,
+                                                          const float *__restrict__ geom, int kind, int V, int R,
+                                                          int C, const MlpImage *__restrict__ img,
+                                                          float *__restrict__ y) {
+    __shared__ MlpImage Wt;
+    const int tR = (R + 15) / 16, tC = (C + 15) / 16;
+    int v, tr, tc;
+    if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot: the whole block
+    load_image(Wt, img);
+    __syncthreads();
+    project_walk<n, false>(c, N0, N1, N2, geom, kind, V, R, C, &Wt, y, v, tr, tc);
+}
+
+template <int n>
+__global__ void __launch_bounds__(256) project_pair_kernel(const float *__restrict__ c, int N0, int N1, int N2,
+                                                           const float *__restrict__ geom, int kind, int V, int R,
+                                                           int C, float *__restrict__ y) {
+    const int tR = (R + 15) / 16, tC = (C + 15) / 16;
+    int v, tr, tc;
+    if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot: the whole block
+    project_walk<n, true>(c, N0, N1, N2, geom, kind, V, R, C, nullptr, y, v, tr, tc);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +446,8 @@ struct RayRecM {     // 80 bytes
     float wf[3];
     float U[3], V[3];
     int d;
-    float pad[2];
+    float iwd;       // 1 / |w_d|
+    float pad;
 };
 
 template <int n>
@@ -435,20 +467,20 @@ __device__ __forceinline__ void fill_ray_m(RayRecM &rec, const float *__restrict
 #pragma unroll
     for (int k = 0; k < 3; ++k) { rec.wf[k] = F.wf[k]; rec.U[k] = F.U[k]; rec.V[k] = F.V[k]; }
     rec.d = d;
+    rec.iwd = L.ok ? (float)(1.0 / fabs(wd)) : 0.0f;
 }
 
-template <int n>
-__global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__restrict__ y, int N0, int N1, int N2,
-                                                              const float *__restrict__ geom,
-                                                              const ViewProj *__restrict__ vps, int kind, int V,
-                                                              int R, int C, const MlpImage *__restrict__ img,
-                                                              float *__restrict__ c) {
-    __shared__ MlpImage Wt;
-    __shared__ RayRecM rays[MRAY_CAP];
-    __shared__ ViewProj vp;
-    __shared__ LocalProj lp;
-    __shared__ int sbox[4];
-    load_image(Wt, img);
+// Coefficient-brick gather: each thread owns one coefficient and sums, view
+// by view, y_m times the footprint over the pixels of its support's shadow.
+// The footprint comes from the network (EXACT = false, 64 pairs per round
+// on the matrix cores) or from the exact piecewise Gauss-Legendre integral
+// (EXACT = true, each lane on its own).
+template <int n, bool EXACT>
+__device__ __forceinline__ void backproject_gather(const float *__restrict__ y, int N0, int N1, int N2,
+                                                   const float *__restrict__ geom, const ViewProj *__restrict__ vps,
+                                                   int kind, int V, int R, int C, const MlpImage *Wt,
+                                                   RayRecM *rays, ViewProj &vp, LocalProj &lp, int *sbox,
+                                                   float *__restrict__ c) {
     constexpr float hf = Degree<n>::h;
     const int nbx = (N0 + MBX - 1) / MBX, nby = (N1 + MBY - 1) / MBY, nbz = (N2 + MBZ - 1) / MBZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -532,6 +564,8 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
                 while (true) {
                     bool have = false;
                     float yv = 0.0f, f3 = 0.0f, f4 = 0.0f, w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+                    float pu1 = 0.0f, pu2 = 0.0f, iwd = 0.0f;
+                    Slopes PS = make_slopes(0.0f, 0.0f);
                     while (live && !have) {
                         const RayRecM &rr = rays[(jj - cj0) * cw + (ii - ci0)];
                         const int d = rr.d;
@@ -544,24 +578,63 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
                         if (chord_nonempty<n>(S, u1, u2)) {
                             have = true;
                             yv = rr.y;
-                            const float x0 = rr.a[0] - xq[0], x1 = rr.a[1] - xq[1], x2 = rr.a[2] - xq[2];
-                            f3 = fmaf(rr.U[0], x0, fmaf(rr.U[1], x1, rr.U[2] * x2));
-                            f4 = fmaf(rr.V[0], x0, fmaf(rr.V[1], x1, rr.V[2] * x2));
-                            w0 = rr.wf[0]; w1 = rr.wf[1]; w2 = rr.wf[2];
+                            if constexpr (EXACT) {
+                                pu1 = u1;
+                                pu2 = u2;
+                                PS = S;
+                                iwd = rr.iwd;
+                            } else {
+                                const float x0 = rr.a[0] - xq[0], x1 = rr.a[1] - xq[1], x2 = rr.a[2] - xq[2];
+                                f3 = fmaf(rr.U[0], x0, fmaf(rr.U[1], x1, rr.U[2] * x2));
+                                f4 = fmaf(rr.V[0], x0, fmaf(rr.V[1], x1, rr.V[2] * x2));
+                                w0 = rr.wf[0]; w1 = rr.wf[1]; w2 = rr.wf[2];
+                            }
                         }
                         ++ii;
                         if (ii > i1) { ii = i0; ++jj; }
                         live = jj <= j1;
                     }
                     if (__ballot(have) == 0) break;
-                    const float f[5] = {w0, w1, w2, f3, f4};
-                    const float fp = mlp_wave(Wt, f);
+                    float fp;
+                    if constexpr (EXACT) {
+                        fp = have ? footprint_slab<n>(PS, pu1, pu2) * iwd : 0.0f;
+                    } else {
+                        const float f[5] = {w0, w1, w2, f3, f4};
+                        fp = mlp_wave(*Wt, f);
+                    }
                     if (have) acc = fmaf(yv, fp, acc);
                 }
             }
         }
     }
     if (mine) c[((int64_t)k2 * N1 + k1) * N0 + k0] = acc;
+}
+
+template <int n>
+__global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__restrict__ y, int N0, int N1, int N2,
+                                                              const float *__restrict__ geom,
+                                                              const ViewProj *__restrict__ vps, int kind, int V,
+                                                              int R, int C, const MlpImage *__restrict__ img,
+                                                              float *__restrict__ c) {
+    __shared__ MlpImage Wt;
+    __shared__ RayRecM rays[MRAY_CAP];
+    __shared__ ViewProj vp;
+    __shared__ LocalProj lp;
+    __shared__ int sbox[4];
+    load_image(Wt, img);
+    backproject_gather<n, false>(y, N0, N1, N2, geom, vps, kind, V, R, C, &Wt, rays, vp, lp, sbox, c);
+}
+
+template <int n>
+__global__ void __launch_bounds__(256) backproject_pair_kernel(const float *__restrict__ y, int N0, int N1, int N2,
+                                                               const float *__restrict__ geom,
+                                                               const ViewProj *__restrict__ vps, int kind, int V,
+                                                               int R, int C, float *__restrict__ c) {
+    __shared__ RayRecM rays[MRAY_CAP];
+    __shared__ ViewProj vp;
+    __shared__ LocalProj lp;
+    __shared__ int sbox[4];
+    backproject_gather<n, true>(y, N0, N1, N2, geom, vps, kind, V, R, C, nullptr, rays, vp, lp, sbox, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,6 +695,42 @@ static hipError_t launch_backproject_mlp_n(const LaunchArgs &a, hipStream_t st) 
     hipLaunchKernelGGL(backproject_mlp_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1], a.N[2],
                        a.geom, a.vproj, a.kind, a.V, a.R, a.C, (const MlpImage *)a.mlp, a.coeffs_out);
     return hipGetLastError();
+}
+
+template <int n>
+static hipError_t launch_project_pair_n(const LaunchArgs &a, hipStream_t st) {
+    const int tR = (a.R + 15) / 16, tC = (a.C + 15) / 16;
+    hipLaunchKernelGGL(project_pair_kernel<n>, dim3((unsigned)fwd_blocks(tR, tC, a.V)), dim3(256), 0, st, a.coeffs,
+                       a.N[0], a.N[1], a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino);
+    return hipGetLastError();
+}
+
+template <int n>
+static hipError_t launch_backproject_pair_n(const LaunchArgs &a, hipStream_t st) {
+    const int nb = ((a.N[0] + MBX - 1) / MBX) * ((a.N[1] + MBY - 1) / MBY) * ((a.N[2] + MBZ - 1) / MBZ);
+    hipLaunchKernelGGL(backproject_pair_kernel<n>, dim3(nb), dim3(256), 0, st, a.sino_in, a.N[0], a.N[1], a.N[2],
+                       a.geom, a.vproj, a.kind, a.V, a.R, a.C, a.coeffs_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_pair(int degree, const LaunchArgs &a, hipStream_t st) {
+    switch (degree) {
+    case 0: return launch_project_pair_n<0>(a, st);
+    case 1: return launch_project_pair_n<1>(a, st);
+    case 2: return launch_project_pair_n<2>(a, st);
+    case 3: return launch_project_pair_n<3>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_backproject_pair(int degree, const LaunchArgs &a, hipStream_t st) {
+    switch (degree) {
+    case 0: return launch_backproject_pair_n<0>(a, st);
+    case 1: return launch_backproject_pair_n<1>(a, st);
+    case 2: return launch_backproject_pair_n<2>(a, st);
+    case 3: return launch_backproject_pair_n<3>(a, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_project_mlp(int degree, const LaunchArgs &a, hipStream_t st) {

@@ -178,9 +178,19 @@ def feature_scale(n: int):
     return scale, shift
 
 
-def make_torch_model(n: int):
+def make_torch_model(degrees):
+    """G independent networks, one per entry of ``degrees``, evaluated side by
+    side with batched products: inputs [G, B, 5] -> outputs [G, B].  A single
+    degree may be given as an int (G = 1)."""
     import torch
     from torch import nn
+
+    degs = [int(degrees)] if np.isscalar(degrees) else [int(d) for d in degrees]
+    G = len(degs)
+
+    def uniform(shape, fan_in):
+        bound = 1.0 / np.sqrt(fan_in)
+        return nn.Parameter(torch.empty(shape).uniform_(-bound, bound))
 
     class FootprintMLP(nn.Module):
         """``quant`` selects the arithmetic of the hidden layers: "fp32";
@@ -188,16 +198,22 @@ def make_torch_model(n: int):
         entering a BF16 layer carried as the sum of two BF16 numbers (its
         rounding and the rounding of the remainder); "bf16" -- weights and
         activations each rounded once to BF16.  Rounding is round to nearest
-        even with a straight-through gradient."""
+        even with a straight-through gradient.  Weights are stored [G, in,
+        out] so that every product is a plain batched product."""
 
         def __init__(self):
             super().__init__()
-            sc, sh = feature_scale(n)
-            self.register_buffer("in_scale", torch.tensor(sc, dtype=torch.float32))
-            self.register_buffer("in_shift", torch.tensor(sh, dtype=torch.float32))
-            self.l1 = nn.Linear(IN_DIM, HIDDEN)
-            self.hidden = nn.ModuleList([nn.Linear(HIDDEN, HIDDEN) for _ in range(DEPTH - 1)])
-            self.out = nn.Linear(HIDDEN, 1)
+            self.degrees = degs
+            sc = np.stack([feature_scale(d)[0] for d in degs])
+            sh = np.stack([feature_scale(d)[1] for d in degs])
+            self.register_buffer("in_scale", torch.tensor(sc, dtype=torch.float32)[:, None, :])
+            self.register_buffer("in_shift", torch.tensor(sh, dtype=torch.float32)[:, None, :])
+            self.w1 = uniform((G, IN_DIM, HIDDEN), IN_DIM)
+            self.b1 = uniform((G, 1, HIDDEN), IN_DIM)
+            self.wh = nn.ParameterList([uniform((G, HIDDEN, HIDDEN), HIDDEN) for _ in range(DEPTH - 1)])
+            self.bh = nn.ParameterList([uniform((G, 1, HIDDEN), HIDDEN) for _ in range(DEPTH - 1)])
+            self.wo = uniform((G, HIDDEN, 1), HIDDEN)
+            self.bo = uniform((G, 1, 1), HIDDEN)
             self.out_scale = 0.5
             self.quant = "fp32"
 
@@ -215,38 +231,44 @@ def make_torch_model(n: int):
             return a
 
         def forward(self, f):
+            if f.dim() == 2:
+                f = f[None]
             z = f * self.in_scale + self.in_shift
-            a = torch.nn.functional.silu(self.l1(z))
-            for lin in self.hidden:
+            a = torch.nn.functional.silu(torch.baddbmm(self.b1, z, self.w1))
+            for W, b in zip(self.wh, self.bh):
                 if self.quant != "fp32":
-                    a = torch.nn.functional.linear(self._act(a), self._bf16(lin.weight), lin.bias)
+                    a = torch.baddbmm(b, self._act(a), self._bf16(W))
                 else:
-                    a = lin(a)
+                    a = torch.baddbmm(b, a, W)
                 a = torch.nn.functional.silu(a)
-            return self.out(a).squeeze(-1) * self.out_scale
+            return torch.baddbmm(self.bo, a, self.wo).squeeze(-1) * self.out_scale
 
     return FootprintMLP()
 
 
-def model_to_blob(model, n: int, seed: int, rel_fp32: float, rel_bf16: float) -> bytes:
-    """Fold the input normalisation into layer 1 and the output scale into the
-    output layer, round the hidden weights to BF16 (RNE) and serialise."""
+def model_to_blob(model, n: int, seed: int, rel_fp32: float, rel_bf16: float, g: int = None) -> bytes:
+    """Network g (default: the one of degree n) of a model: fold the input
+    normalisation into layer 1 and the output scale into the output layer,
+    round the hidden weights to BF16 (RNE) and serialise ([out][in] rows)."""
     import torch
 
+    if g is None:
+        g = model.degrees.index(n)
     with torch.no_grad():
-        sc = model.in_scale.detach().cpu().double().numpy()
-        sh = model.in_shift.detach().cpu().double().numpy()
-        W1 = model.l1.weight.detach().cpu().double().numpy()
-        b1 = model.l1.bias.detach().cpu().double().numpy()
+        sc = model.in_scale[g, 0].detach().cpu().double().numpy()
+        sh = model.in_shift[g, 0].detach().cpu().double().numpy()
+        W1 = model.w1[g].detach().cpu().double().numpy().T          # [out][in]
+        b1 = model.b1[g, 0].detach().cpu().double().numpy()
         W1f = (W1 * sc[None, :]).astype(np.float32)
         b1f = (b1 + W1 @ sh).astype(np.float32)
         parts = [W1f.tobytes(), b1f.tobytes()]
-        for lin in model.hidden:
-            wb = lin.weight.detach().cpu().float().to(torch.bfloat16).view(torch.int16).numpy().astype(np.int16)
+        for W, b in zip(model.wh, model.bh):
+            wt = W[g].detach().cpu().float().t().contiguous()
+            wb = wt.to(torch.bfloat16).view(torch.int16).numpy().astype(np.int16)
             parts.append(wb.tobytes())
-            parts.append(lin.bias.detach().cpu().float().numpy().astype(np.float32).tobytes())
-        wo = (model.out.weight.detach().cpu().double().numpy().reshape(-1) * model.out_scale).astype(np.float32)
-        bo = np.array([model.out.bias.detach().cpu().double().item() * model.out_scale], dtype=np.float32)
+            parts.append(b[g, 0].detach().cpu().float().numpy().astype(np.float32).tobytes())
+        wo = (model.wo[g, :, 0].detach().cpu().double().numpy() * model.out_scale).astype(np.float32)
+        bo = np.array([model.bo[g, 0, 0].detach().cpu().double().item() * model.out_scale], dtype=np.float32)
         parts += [wo.tobytes(), bo.tobytes()]
     header = struct.pack(HEADER_FMT, MAGIC, VERSION, n, IN_DIM, HIDDEN, DEPTH, ACT_SILU, FOLD_ID, seed,
                          float(rel_fp32), float(rel_bf16))

@@ -53,7 +53,9 @@ def _check_shape(t, shape, name: str):
 
 
 class Context:
-    """An ss_ctx: degree n in 0..3, form 'quad' (exact FP32) or 'mlp' (BF16 network)."""
+    """An ss_ctx: degree n in 0..3, form 'quad' (exact FP32, knot-cell walk),
+    'mlp' (BF16 network) or 'pair' (exact FP32 per (line, basis) pair on the
+    network form's walk)."""
 
     def __init__(self, degree: int = 3, form: str = "quad", device: int = 0, weights=None):
         lib = _lib.load()
@@ -224,13 +226,16 @@ def project(c: torch.Tensor, projector: Projector) -> torch.Tensor:
     return Project.apply(c, projector)
 
 
-def cgls(projector: Projector, y: torch.Tensor, iters: int = 50, x0=None, callback=None):
+def cgls(projector: Projector, y: torch.Tensor, iters: int = 50, x0=None, callback=None,
+         residuals: bool = False):
     """CGLS for min ||P x - y||^2 (eq. (6)), x_0 = 0 unless given.
 
     Vectors stay FP32 on the device; the inner products are accumulated in
     FP64 and the step length alpha and ratio beta are formed in FP64 on the
     device, so the loop never synchronises with the host.  Returns
-    (x, history) with history the device FP64 tensor of ||A^T r_k||^2."""
+    (x, history) with history the device FP64 tensor of ||A^T r_k||^2; with
+    ``residuals`` also the device FP64 tensor of ||r_k||^2 (one more inner
+    product per iteration)."""
     ctx = projector.ctx
     dev = y.device
     f64 = dict(dtype=torch.float64, device=dev)
@@ -247,8 +252,11 @@ def cgls(projector: Projector, y: torch.Tensor, iters: int = 50, x0=None, callba
     alpha = torch.empty((), **f64)
     beta = torch.empty((), **f64)
     hist = torch.empty(iters + 1, **f64)
+    rhist = torch.empty(iters + 1, **f64) if residuals else None
     ctx.dot_f64(s, s, gamma)
     hist[0] = gamma
+    if residuals:
+        ctx.dot_f64(r, r, rhist[0])
     for k in range(iters):
         projector.forward(p, q)
         ctx.dot_f64(q, q, qq)
@@ -261,6 +269,10 @@ def cgls(projector: Projector, y: torch.Tensor, iters: int = 50, x0=None, callba
         ctx.xpay(beta, s, p)
         gamma, gamma_new = gamma_new, gamma
         hist[k + 1] = gamma
+        if residuals:
+            ctx.dot_f64(r, r, rhist[k + 1])
         if callback is not None:
             callback(k, x, r)
+    if residuals:
+        return x, hist, rhist
     return x, hist

@@ -31,8 +31,10 @@ a tolerance.  This script follows those steps with these choices:
 A run can be cut into pieces (``--time-limit`` seconds each): the state is
 kept in ``--ckpt`` and the next call with the same arguments resumes it.
 
-Usage:  python -m paper_2511_11078_amd.train_footprint --degree 3 --device cuda \\
-            --ckpt train_n3.pt --out paper_2511_11078_amd/weights/mlp_n3.bin
+Several degrees train side by side, one network each, in batched products.
+
+Usage:  python -m paper_2511_11078_amd.train_footprint --degrees 3,2,1 --device cuda \\
+            --ckpt train.pt --out-dir paper_2511_11078_amd/weights
 """
 from __future__ import annotations
 
@@ -98,20 +100,35 @@ def make_dataset(n: int, count: int, seed: int, device="cpu"):
     return f.to(torch.float32), y.to(torch.float32)
 
 
-def rel_l2(model, f, y, quant: str, chunk: int = 1 << 18) -> float:
+def make_group_dataset(degrees, count: int, seed: int, device="cpu"):
+    """Stacked datasets of several degrees: features [G, count, 5], labels [G, count]."""
+    import torch
+
+    fs, ys = [], []
+    for g, n in enumerate(degrees):
+        f, y = make_dataset(n, count, seed + 104729 * g, device)
+        fs.append(f)
+        ys.append(y)
+    return torch.stack(fs), torch.stack(ys)
+
+
+def rel_l2(model, f, y, quant: str, chunk: int = 1 << 18):
+    """Validation relative L2 error of each network of the model."""
     import torch
 
     prev = model.quant
     model.quant = quant
-    num = den = 0.0
+    G = f.shape[0]
+    num = torch.zeros(G, dtype=torch.float64, device=f.device)
+    den = torch.zeros(G, dtype=torch.float64, device=f.device)
     with torch.no_grad():
-        for s in range(0, f.shape[0], chunk):
-            p = model(f[s:s + chunk]).double()
-            t = y[s:s + chunk].double()
-            num += float(((p - t) ** 2).sum())
-            den += float((t ** 2).sum())
+        for s in range(0, f.shape[1], chunk):
+            p = model(f[:, s:s + chunk]).double()
+            t = y[:, s:s + chunk].double()
+            num += ((p - t) ** 2).sum(1)
+            den += (t ** 2).sum(1)
     model.quant = prev
-    return math.sqrt(num / den)
+    return [float(v) for v in torch.sqrt(num / den).cpu()]
 
 
 def lr_at(step: int, steps: int, qat_steps: int, lr: float, warmup: int = 2000) -> float:
@@ -124,48 +141,57 @@ def lr_at(step: int, steps: int, qat_steps: int, lr: float, warmup: int = 2000) 
     return 1e-8 + (0.03 * lr) * 0.5 * (1 + math.cos(math.pi * p))
 
 
-def refit_fp32_params(model, f, y, iters: int, log):
+def _loss(model, f, y, inv_ms):
+    """Sum over the networks of their mean squared error relative to the mean
+    squared label (each network weighs the same)."""
+    p = model(f)
+    return (((p - y) ** 2).mean(1) * inv_ms).sum()
+
+
+def refit_fp32_params(model, f, y, inv_ms, iters: int, log):
     """Freeze the hidden weights at their BF16 values and refit the FP32
     parameters (layer 1, biases, output layer) by full-batch L-BFGS in the
     kernel's arithmetic."""
     import torch
 
     with torch.no_grad():
-        for lin in model.hidden:
-            lin.weight.copy_(lin.weight.to(torch.bfloat16).to(torch.float32))
-            lin.weight.requires_grad_(False)
-    params = [model.l1.weight, model.l1.bias, model.out.weight, model.out.bias] + [l.bias for l in model.hidden]
+        for W in model.wh:
+            W.copy_(W.to(torch.bfloat16).to(torch.float32))
+            W.requires_grad_(False)
+    params = [model.w1, model.b1, model.wo, model.bo] + list(model.bh)
     model.quant = "split"
     opt = torch.optim.LBFGS(params, lr=1.0, max_iter=iters, history_size=50, tolerance_grad=0.0,
                             tolerance_change=0.0, line_search_fn="strong_wolfe")
-    chunk = 1 << 20
-    scale = 1.0 / float((y.double() ** 2).mean())
+    chunk = 1 << 19
+    nchunks = (f.shape[1] + chunk - 1) // chunk
 
     def closure():
         opt.zero_grad(set_to_none=True)
         total = 0.0
-        for s in range(0, f.shape[0], chunk):
-            p = model(f[s:s + chunk])
-            loss = ((p - y[s:s + chunk]) ** 2).sum() * (scale / f.shape[0])
+        for s in range(0, f.shape[1], chunk):
+            loss = _loss(model, f[:, s:s + chunk], y[:, s:s + chunk], inv_ms) / nchunks
             loss.backward()
             total += float(loss.detach())
         return torch.tensor(total)
 
     loss = opt.step(closure)
     log(f"refit: {iters} L-BFGS iterations, relative loss {float(loss):.3e}")
-    for lin in model.hidden:
-        lin.weight.requires_grad_(True)
+    for W in model.wh:
+        W.requires_grad_(True)
 
 
-def train(n: int, steps: int, qat_steps: int, batch: int, lr: float, seed: int, out: str, threads: int,
+def train(degrees, steps: int, qat_steps: int, batch: int, lr: float, seed: int, out_dir: str, threads: int,
           pool: int, device: str, ckpt: str | None, time_limit: float, refit_iters: int, refit_samples: int,
           log=print):
+    """Train one network per degree, side by side; write mlp_n<degree>.bin
+    into out_dir when the step budget is reached (None before that)."""
     import torch
 
     torch.set_num_threads(threads)
     torch.manual_seed(seed)
     dev = torch.device(device)
-    model = fn.make_torch_model(n).to(dev)
+    degrees = [int(d) for d in degrees]
+    model = fn.make_torch_model(degrees).to(dev)
     opt = torch.optim.Adam(model.parameters(), lr=lr)
     start = 0
     if ckpt and os.path.exists(ckpt):
@@ -174,82 +200,89 @@ def train(n: int, steps: int, qat_steps: int, batch: int, lr: float, seed: int, 
         opt.load_state_dict(st["opt"])
         start = int(st["step"])
         log(f"resumed from {ckpt} at step {start}")
-    fval, yval = make_dataset(n, 1_000_000, seed + 1000, dev)
+    fval, yval = make_group_dataset(degrees, 1_000_000, seed + 1000, dev)
+    inv_ms = 1.0 / (yval.double() ** 2).mean(1).float()
     total = steps + qat_steps
     t0 = time.time()
-    last_log = 0.0
+    last_log = -1e9
     pool_every = max(1, pool // batch)
     gen = torch.Generator(device=dev)
     step = start
     fpool = ypool = None
+
+    def fmt(v):
+        return " ".join(f"n{d}:{e:.3e}" for d, e in zip(degrees, v))
+
     while step < total:
         if fpool is None or (step - start) % pool_every == 0:
-            fpool, ypool = make_dataset(n, pool, seed + 7919 * step + 1, dev)
+            fpool, ypool = make_group_dataset(degrees, pool, seed + 7919 * step + 1, dev)
             gen.manual_seed(seed + step)
         model.quant = "split" if step >= steps else "fp32"
         cur = lr_at(step, steps, qat_steps, lr)
         for g in opt.param_groups:
             g["lr"] = cur
-        idx = torch.randint(0, fpool.shape[0], (batch,), generator=gen, device=dev)
-        pred = model(fpool[idx])
-        loss = torch.mean((pred - ypool[idx]) ** 2)
+        idx = torch.randint(0, fpool.shape[1], (batch,), generator=gen, device=dev)
+        loss = _loss(model, fpool[:, idx], ypool[:, idx], inv_ms)
         opt.zero_grad(set_to_none=True)
         loss.backward()
         opt.step()
         step += 1
         now = time.time() - t0
-        if step % 10000 == 0 or step == total or now - last_log > 45.0:
+        if step % 20000 == 0 or step == total or now - last_log > 30.0:
             last_log = now
-            r32 = rel_l2(model, fval, yval, "fp32")
-            rq = rel_l2(model, fval, yval, "split")
-            log(f"step {step:7d}/{total} lr {cur:.2e} loss {loss.item():.3e} val_rel_fp32 {r32:.3e} "
-                f"val_rel_kernel {rq:.3e} t {now:.0f}s")
+            log(f"step {step:7d}/{total} lr {cur:.2e} loss {loss.item():.3e} "
+                f"val fp32 [{fmt(rel_l2(model, fval, yval, 'fp32'))}] "
+                f"kernel [{fmt(rel_l2(model, fval, yval, 'split'))}] t {now:.0f}s")
         if ckpt and (now > time_limit or step == total):
             torch.save({"model": model.state_dict(), "opt": opt.state_dict(), "step": step}, ckpt)
             if step < total:
                 log(f"time limit: state saved to {ckpt} at step {step}")
                 return None
     if refit_iters > 0:
-        fr, yr = make_dataset(n, refit_samples, seed + 2000, dev)
+        fr, yr = make_group_dataset(degrees, refit_samples, seed + 2000, dev)
         before = rel_l2(model, fval, yval, "split")
         saved = {k: v.clone() for k, v in model.state_dict().items()}
-        refit_fp32_params(model, fr, yr, refit_iters, log)
+        refit_fp32_params(model, fr, yr, inv_ms, refit_iters, log)
         after = rel_l2(model, fval, yval, "split")
-        log(f"refit: validation rel-L2 in the kernel's arithmetic {before:.3e} -> {after:.3e}")
-        if not after < before:
+        log(f"refit: validation rel-L2 in the kernel's arithmetic [{fmt(before)}] -> [{fmt(after)}]")
+        if not sum(a * a for a in after) < sum(b * b for b in before):
             model.load_state_dict(saved)
+            log("refit: not kept")
     model.quant = "fp32"
     r32 = rel_l2(model, fval, yval, "fp32")
     rq = rel_l2(model, fval, yval, "split")
     r1 = rel_l2(model, fval, yval, "bf16")
-    blob = fn.model_to_blob(model, n, seed, r32, rq)
-    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
-    with open(out, "wb") as fh:
-        fh.write(blob)
-    log(f"wrote {out}: val rel-L2 fp32 {r32:.3e}, kernel arithmetic {rq:.3e} "
-        f"(activations rounded once to BF16: {r1:.3e})")
+    os.makedirs(out_dir, exist_ok=True)
+    for g, n in enumerate(degrees):
+        blob = fn.model_to_blob(model, n, seed, r32[g], rq[g], g=g)
+        path = os.path.join(out_dir, f"mlp_n{n}.bin")
+        with open(path, "wb") as fh:
+            fh.write(blob)
+        log(f"wrote {path}: val rel-L2 fp32 {r32[g]:.3e}, kernel arithmetic {rq[g]:.3e} "
+            f"(activations rounded once to BF16: {r1[g]:.3e})")
     return model
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--degrees", default="3", help="comma-separated degrees, trained side by side")
     ap.add_argument("--steps", type=int, default=300000)
-    ap.add_argument("--qat-steps", type=int, default=40000)
+    ap.add_argument("--qat-steps", type=int, default=30000)
     ap.add_argument("--batch", type=int, default=65536)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1.5e-3)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--pool", type=int, default=4_000_000)
     ap.add_argument("--device", default="cpu")
     ap.add_argument("--ckpt", default=None, help="state file for runs cut into pieces")
     ap.add_argument("--time-limit", type=float, default=float("inf"), help="seconds before saving and stopping")
-    ap.add_argument("--refit-iters", type=int, default=500)
-    ap.add_argument("--refit-samples", type=int, default=4_000_000)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--refit-iters", type=int, default=300)
+    ap.add_argument("--refit-samples", type=int, default=2_000_000)
+    ap.add_argument("--out-dir", required=True, help="where mlp_n<degree>.bin are written")
     a = ap.parse_args()
-    train(a.degree, a.steps, a.qat_steps, a.batch, a.lr, a.seed, a.out, a.threads, a.pool, a.device, a.ckpt,
-          a.time_limit, a.refit_iters, a.refit_samples, log=lambda s: print(s, flush=True))
+    train([int(d) for d in a.degrees.split(",")], a.steps, a.qat_steps, a.batch, a.lr, a.seed, a.out_dir,
+          a.threads, a.pool, a.device, a.ckpt, a.time_limit, a.refit_iters, a.refit_samples,
+          log=lambda s: print(s, flush=True))
 
 
 if __name__ == "__main__":

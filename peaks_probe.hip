@@ -1,12 +1,18 @@
 // Peak-rate probe of the GPU the transform runs on: a device-to-device copy
-// (HBM bandwidth), independent chains of FP32 FMA in the non-packed form the
-// kernels are compiled to (once with a scalar-register operand, once with
-// vector-register operands only: the two issue at different rates), exp +
-// reciprocal pairs (the sigmoid of the network form's activation) and
-// v_mfma_f32_32x32x16_bf16.  It is a measurement aid for the roofline
-// denominators, separate from the library: `python -m
-// paper_2511_11078_amd.build` builds it next to the library, and it prints
-// one line per rate (best of three launches, HIP events).
+// (HBM bandwidth), reads of a buffer that stays in the L2 caches and of one
+// that stays in the last-level (infinity) cache, independent chains of FP32
+// FMA in the non-packed form the kernels are compiled to (once with a
+// scalar-register operand, once with vector-register operands only: the two
+// issue at different rates), exp + reciprocal pairs (the sigmoid of the
+// network form's activation) and v_mfma_f32_32x32x16_bf16.  It is a
+// measurement aid for the roofline denominators, not part of the library.
+// Build and run from the repository root:
+//
+//   hipcc -x hip -O3 -std=c++17 --offload-arch=gfx950 -Xclang -target-feature \
+//         -Xclang -packed-fp32-ops peaks_probe.hip -o _build/peaks_probe
+//   ./_build/peaks_probe
+//
+// It prints one line per rate (best of three launches, HIP events).
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdlib>
@@ -26,6 +32,26 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __global__ void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst, long n) {
     const long stride = (long)gridDim.x * blockDim.x;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// Every block reads the whole buffer of n float4 `reps` times, starting at a
+// block-dependent offset, so that a CU streams far more than its L1 holds
+// and every access is served by the level of the hierarchy that holds the
+// buffer (L2 when it fits an XCD's 4 MB L2, the last-level cache when it
+// fits its 256 MB).  The sum keeps the loads alive.
+__global__ void __launch_bounds__(256) read_kernel(const float4 *__restrict__ src, long n, int reps,
+                                                   float *__restrict__ out) {
+    float a = 0.0f;
+    const long start = ((long)blockIdx.x * 7919) % n;
+    for (int r = 0; r < reps; ++r) {
+        for (long i = threadIdx.x; i < n; i += blockDim.x) {
+            long k = start + i;
+            if (k >= n) k -= n;
+            const float4 v = src[k];
+            a += v.x + v.y + v.z + v.w;
+        }
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = a;
 }
 
 constexpr int CHAINS = 16;
@@ -138,6 +164,29 @@ int main() {
     std::printf("copy 1 GiB: %.3f ms, %.0f GB/s (read + write)\n", tc, 2.0 * bytes / (tc * 1e-3) / 1e9);
     CHECK(hipFree(src));
     CHECK(hipFree(dst));
+
+    // cache-resident reads: 2 MiB (fits each XCD's L2) and 128 MiB (fits the
+    // last-level cache, not the L2); one warm-up pass brings the buffer in
+    {
+        float *rout = nullptr;
+        const int rblocks = cus * 4;
+        CHECK(hipMalloc(&rout, sizeof(float) * rblocks * 256));
+        for (long mib : {2L, 128L}) {
+            const long rb = mib << 20, rn = rb / 16;
+            float4 *buf = nullptr;
+            CHECK(hipMalloc(&buf, rb));
+            CHECK(hipMemset(buf, 0, rb));
+            const int reps = mib <= 2 ? 8 : 1;
+            const int nblk = rblocks;
+            read_kernel<<<nblk, 256>>>(buf, rn, 1, rout);
+            const float tr = best_ms([&] { read_kernel<<<nblk, 256>>>(buf, rn, reps, rout); });
+            const double moved = (double)nblk * reps * rb;
+            std::printf("read %ld MiB buffer, %d blocks x %d passes: %.3f ms, %.0f GB/s\n", mib, nblk, reps, tr,
+                        moved / (tr * 1e-3) / 1e9);
+            CHECK(hipFree(buf));
+        }
+        CHECK(hipFree(rout));
+    }
 
     const int blocks = cus * 8, threads = 256;
     float *out = nullptr;

@@ -82,6 +82,8 @@ def test_create_argument_errors_need_no_gpu():
     assert _create(0, 1)[0] == _lib.SS_EUNSUPPORTED
     assert _create(3, 1)[0] == _lib.SS_EBLOB            # no blob
     assert _create(3, 0, b"x" * 8)[0] == _lib.SS_EINVAL  # blob for the quadrature form
+    assert _create(3, 2, b"x" * 8)[0] == _lib.SS_EINVAL  # blob for the per-pair exact form
+    assert _create(3, 3)[0] == _lib.SS_EINVAL            # no such form
     good = bytearray(footprint_net.blob_bytes())
     assert _create(3, 1, bytes(good[:-1]))[0] == _lib.SS_EBLOB    # wrong size
     assert _create(3, 1, bytes(good))[0] == _lib.SS_EBLOB         # bad magic

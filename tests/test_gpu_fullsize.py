@@ -31,7 +31,10 @@ def _volume(wl):
     return _VOLUMES[wl.name]
 
 
-def _check(wl_name, form, n_rays=16384, n_coefs=4096, views=None):
+def _check(wl_name, form, n_rays=16384, n_coefs=4096, views=None, noise_adjoint=False):
+    """Forward on the workload's volume, and the adjoint of its own forward
+    projection (and, with noise_adjoint, also of a Gaussian noise sinogram,
+    seed 9, whose back-projection does not average per-pair errors away)."""
     wl = configs.get(wl_name)
     geom = wl.geometry() if views is None else wl.geometry().subset_views(*views)
     dims = wl.dims
@@ -46,9 +49,18 @@ def _check(wl_name, form, n_rays=16384, n_coefs=4096, views=None):
     y_np = to_np(y)
     ef = rel_l2(y_np.ravel()[rays], oracle.project(c_np, geom, wl.degree, rays=rays))
     eb = rel_l2(to_np(b).ravel()[coefs], oracle.backproject_subset(y_np, geom, dims, wl.degree, coefs=coefs))
-    say(f"  {wl_name} {form}: forward rel-L2 {ef:.3e}, adjoint rel-L2 {eb:.3e}")
+    msg = f"  {wl_name} {form}: forward rel-L2 {ef:.3e}, adjoint rel-L2 {eb:.3e}"
+    ebn = None
+    if noise_adjoint:
+        rng = np.random.default_rng(9)
+        yn = rng.standard_normal(y_np.shape).astype(np.float32)
+        bn = ctx.backproject(to_gpu(yn), geom, dims)
+        torch.cuda.synchronize()
+        ebn = rel_l2(to_np(bn).ravel()[coefs], oracle.backproject_subset(yn, geom, dims, wl.degree, coefs=coefs))
+        msg += f", adjoint of noise rel-L2 {ebn:.3e}"
+    say(msg)
     ctx.close()
-    return ef, eb
+    return (ef, eb) if not noise_adjoint else (ef, eb, ebn)
 
 
 def test_parallel_128_quad():
@@ -96,14 +108,25 @@ def test_cone_256_quad():
 def test_parallel_128_mlp():
     say("parallel_128 mlp")
     ef, eb = _check("parallel_128", "mlp", n_coefs=1024)
-    assert ef <= TOL_MLP and eb <= 2 * TOL_MLP
+    assert ef <= TOL_MLP and eb <= TOL_MLP
+
+
+@pytest.mark.skipif(not os.path.exists(default_weights(3)), reason="no trained network weights")
+def test_cone_256_mlp():
+    """The benchmark workload with the network form, in the launch the
+    benchmark times (all 360 views in one call): 16,384 sampled lines and
+    1,024 sampled coefficients, the adjoint of the forward projection and of
+    a noise sinogram."""
+    say("cone_256 mlp")
+    ef, eb, ebn = _check("cone_256", "mlp", n_coefs=1024, noise_adjoint=True)
+    assert ef <= TOL_MLP and eb <= TOL_MLP and ebn <= TOL_MLP
 
 
 @pytest.mark.skipif(not os.path.exists(default_weights(3)), reason="no trained network weights")
 def test_cone_512_one_batch_mlp():
     say("cone_512, views 0..31, mlp")
     ef, eb = _check("cone_512", "mlp", n_rays=4096, n_coefs=256, views=(0, 32))
-    assert ef <= TOL_MLP and eb <= 2 * TOL_MLP
+    assert ef <= TOL_MLP and eb <= TOL_MLP
 
 
 def test_cone_512_one_batch_quad():

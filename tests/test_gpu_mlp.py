@@ -4,13 +4,16 @@ Two separate questions:
 
 1. Does the kernel compute the network the blob defines, on exactly the
    pairs the quadrature form visits?  Compared with a numpy evaluation of
-   the same weights (FP32 features and layer 1, BF16-rounded activations
-   into the three hidden layers, FP32 output), per footprint and per
-   projection (brute-force pair enumeration on small volumes), plus the
-   dot-product test of the network forward/adjoint pair.
+   the same weights in the kernel's arithmetic (FP32 features and layer 1,
+   BF16 hidden weights, each activation entering a hidden layer as the sum
+   of two BF16 numbers, FP32 output), per footprint and per projection
+   (brute-force pair enumeration on small volumes), plus the dot-product
+   test of the network forward/adjoint pair.
 2. How far is the network form from the exact transform?  Relative L2
-   error against the FP64 oracle, reported and bounded (the network's own
-   fitting error is in the blob header).
+   error against the FP64 oracle, in both directions (the adjoint of a
+   noise sinogram, which does not average the per-pair errors away),
+   bounded by the stated 1e-3 (the network's own fitting error is in the
+   blob header).
 """
 import os
 
@@ -75,9 +78,9 @@ def test_network_footprint_matches_numpy(mctx, blob):
     e = rel_l2(got, want)
     mx = np.abs(got - want).max()
     say(f"  rel-L2 {e:.3e}, max abs diff {mx:.3e}")
-    # BF16 rounding of activations may flip by one unit where the FP32
-    # pre-activations differ in their last bits
-    assert e <= 2e-4 and mx <= 2e-3 * np.abs(want).max()
+    # the split activations keep about 16 bits: only FP32 rounding of the
+    # features, the layer-1 sums and the SiLU separates kernel and numpy
+    assert e <= 2e-5 and mx <= 2e-4 * np.abs(want).max()
 
 
 def test_network_gate_is_exact(mctx):
@@ -109,7 +112,7 @@ def test_network_projection_matches_pair_enumeration(mctx, blob, kind):
     want = _pairs_reference(blob, 3, c, geom)
     e = rel_l2(got, want)
     say(f"  rel-L2 {e:.3e}")
-    assert e <= 2e-4
+    assert e <= 2e-5
 
 
 @pytest.mark.parametrize("kind", ["parallel", "cone", "cone_source_inside"])
@@ -131,10 +134,10 @@ def test_network_dot_product_test(mctx, kind):
     rhs = float((x.double() * Aty.double()).sum())
     rel = abs(lhs - rhs) / (float(Ax.double().norm()) * float(y.double().norm()))
     say(f"  dot-test relative mismatch {rel:.3e}")
-    # forward and adjoint evaluate the same network on the same pairs; the
-    # FP32 feature rounding differs (crossing point vs re-based anchor) and
-    # can flip a BF16 activation
-    assert rel <= 1e-4
+    # forward and adjoint evaluate the same network on the same pairs; only
+    # the FP32 rounding of the features differs (crossing point vs re-based
+    # anchor)
+    assert rel <= 1e-5
 
 
 def test_network_vs_oracle_small_parallel_32(mctx, blob):
@@ -153,6 +156,4 @@ def test_network_vs_oracle_small_parallel_32(mctx, blob):
     eb = rel_l2(gb, wb)
     say(f"  forward rel-L2 {e:.3e}, adjoint rel-L2 {eb:.3e} (blob fit fp32 {blob['rel_fp32']:.2e}, "
         f"bf16 {blob['rel_bf16']:.2e})")
-    # trained degree-3 weights: footprint fit 2.3e-3 (BF16); line sums average
-    # the per-pair errors, a noise sinogram back-projected does not
-    assert e <= 1e-3 and eb <= 5e-3
+    assert e <= 1e-3 and eb <= 1e-3
