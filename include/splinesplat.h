@@ -144,6 +144,25 @@ ss_status ss_project(ss_ctx *ctx, const float *d_coeffs, const int64_t dims[3],
 ss_status ss_backproject(ss_ctx *ctx, const float *d_sino, const ss_geometry *geom,
                          const int64_t dims[3], float *d_coeffs, void *hip_stream);
 
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes what ss_project computes with a SS_FORM_QUAD_FP32
+ * context of degree `degree` (0..3) on HIP device `device`, with the same
+ * kernels and bit-identical results, but needs no context and calls no
+ * allocating routine: the view vectors and the zero-padded coefficients go
+ * into a static device array of the library, SS_STATIC_SCRATCH_BYTES per GPU,
+ * held until the process ends.  It must hold 12 n_views floats (rounded up
+ * to 64) plus (dims[k] + 2 degree + 2) floats per axis of padded volume
+ * (256^3 fits at every degree); larger problems return SS_EINVAL before
+ * anything is enqueued.  The view vectors are copied from the caller's host
+ * memory with hipMemcpyAsync on hip_stream.  Every call on one GPU uses that
+ * GPU's array, which keeps the last call's contents: calls that overlap in
+ * time on one GPU race (order them on one stream).  Other errors as
+ * ss_project. */
+#define SS_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+ss_status ss_project_noalloc(int device, int degree, const float *d_coeffs, const int64_t dims[3],
+                             const ss_geometry *geom, float *d_sino, void *hip_stream);
+
 /* Evaluate the context's footprint P phi(w, x) = int phi(x + t w) dt (the
  * contribution of eq. (4)) for `count` pairs: d_dirs FP32 [count][3] (unit
  * directions), d_offsets FP32 [count][3] (any point of the line relative to

@@ -342,6 +342,49 @@ ss_status ss_backproject(ss_ctx *ctx, const float *d_sino, const ss_geometry *ge
     return run_transform(ctx, false, d_sino, dims, geom, d_coeffs, hip_stream);
 }
 
+ss_status ss_project_noalloc(int device, int degree, const float *d_coeffs, const int64_t dims[3],
+                             const ss_geometry *geom, float *d_sino, void *hip_stream) {
+    if (degree < 0 || degree > 3) return fail(SS_EINVAL, "degree %d outside 0..3", degree);
+    if (!d_coeffs) return fail(SS_EINVAL, "d_coeffs is NULL");
+    if (!d_sino) return fail(SS_EINVAL, "d_sino is NULL");
+    if (ss_status s = check_dims(dims)) return s;
+    if (ss_status s = check_geom(geom)) return s;
+    const int N[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+    // view vectors first (rounded up to 256 bytes), then the padded volume
+    const int64_t geom_floats = ((int64_t)geom->n_views * 12 + 63) / 64 * 64;
+    const int64_t padded = ss::project_quad_scratch_floats(degree, N);
+    if (geom_floats + padded > ss::STATIC_SCRATCH_FLOATS)
+        return fail(SS_EINVAL, "ss_project_noalloc: %lld view floats + %lld padded coefficients exceed the %lld-float "
+                    "static scratch", (long long)geom_floats, (long long)padded, (long long)ss::STATIC_SCRATCH_FLOATS);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(SS_EINVAL, "device %d not in [0, %d)", device, ndev);
+    DeviceGuard guard(device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
+    float *base = nullptr;
+    if ((e = ss::static_scratch_address(device, &base)) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((e = hipMemcpyAsync(base, geom->vecs, (size_t)geom->n_views * 12 * sizeof(float), hipMemcpyHostToDevice,
+                            st)) != hipSuccess)
+        return hip_fail(e, "geometry copy");
+    ss::LaunchArgs a{};
+    a.coeffs = d_coeffs;
+    a.sino = d_sino;
+    a.geom = base;
+    a.N[0] = N[0];
+    a.N[1] = N[1];
+    a.N[2] = N[2];
+    a.kind = geom->kind;
+    a.V = geom->n_views;
+    a.R = geom->det_rows;
+    a.C = geom->det_cols;
+    a.scratch = base + geom_floats;
+    a.scratch_floats = ss::STATIC_SCRATCH_FLOATS - geom_floats;
+    if ((e = ss::launch_project_quad(degree, a, st)) != hipSuccess) return hip_fail(e, "project launch");
+    return SS_OK;
+}
+
 ss_status ss_footprint(ss_ctx *ctx, const float *d_dirs, const float *d_offsets, int64_t count, float *d_out,
                        void *hip_stream) {
     if (ss_status s = check_ctx(ctx)) return s;

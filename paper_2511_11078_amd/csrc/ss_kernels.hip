@@ -12,6 +12,7 @@
 #include "ss_kernels.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace ss {
 
@@ -763,6 +764,35 @@ hipError_t launch_project_quad(int degree, const LaunchArgs &a, hipStream_t st) 
     case 3: return launch_project_n<3>(a, st);
     }
     return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward: a file-scope device array holds the view vectors
+// and the zero-padded coefficients.  Host code never passes `scratch` itself
+// to a kernel (in host code the name is a host-side stand-in); it asks the
+// runtime, once per device with that device current, for the array's device
+// address and passes that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[STATIC_SCRATCH_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t static_scratch_address(int device, float **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<float *>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_backproject_quad(int degree, const LaunchArgs &a, hipStream_t st) {

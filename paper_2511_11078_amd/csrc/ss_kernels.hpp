@@ -48,6 +48,14 @@ int64_t backproject_quad_scratch_floats(int degree, const int N[3]);
 int64_t project_quad_scratch_floats(int degree, const int N[3]);
 
 hipError_t launch_project_quad(int degree, const LaunchArgs &a, hipStream_t st);
+
+// Static scratch of the allocation-free forward (ss_project_noalloc): view
+// vectors, then the zero-padded coefficients, in one file-scope device array
+// of STATIC_SCRATCH_FLOATS floats per GPU.  static_scratch_address returns
+// its device address on `device`, which must be the current device (looked
+// up once per device, then cached).
+constexpr int64_t STATIC_SCRATCH_FLOATS = (int64_t)24 << 20;  // 96 MiB
+hipError_t static_scratch_address(int device, float **ptr);
 hipError_t launch_backproject_quad(int degree, const LaunchArgs &a, hipStream_t st);
 hipError_t launch_footprint_quad(int degree, const float *dirs, const float *offs, int count, float *out,
                                  hipStream_t st);

@@ -167,6 +167,27 @@ class Context:
         return y
 
 
+def project_noalloc(c: torch.Tensor, geom, degree: int = 3, out: torch.Tensor | None = None) -> torch.Tensor:
+    """ss_project_noalloc: the quadrature-form forward of ``Context.project``
+    without a context and without any allocation by the library (its
+    scratch is a static device array per GPU; calls on one GPU must not
+    overlap in time).  ``out`` [V, R, C] is allocated here when not given."""
+    lib = _lib.load()
+    if c.dim() != 3:
+        raise ValueError("coefficients must be [N3, N2, N1]")
+    dims = (c.shape[2], c.shape[1], c.shape[0])
+    shape = (geom.n_views, geom.det_rows, geom.det_cols)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=c.device)
+    _check_shape(out, shape, "out")
+    device = c.device.index if c.device.index is not None else 0
+    g = _lib.GeometryArg(geom)
+    _lib.check(lib.ss_project_noalloc(device, int(degree), _dev_ptr(c, torch.float32, device, "c"),
+                                      _lib.dims_arg(dims), g.ref(), _dev_ptr(out, torch.float32, device, "out"),
+                                      _stream(device)))
+    return out
+
+
 class Projector:
     """P_phi of eq. (7) for coefficient volumes of size ``dims`` = (N1, N2, N3)
     and a fixed acquisition geometry."""

@@ -150,3 +150,14 @@ def test_binding_rejects_wrongly_sized_buffers():
         ctx.dot_f64(torch.zeros(4), torch.zeros(4), out=torch.zeros(2, dtype=torch.float64))
     with pytest.raises(ValueError):
         ctx.axpy(torch.zeros(2, dtype=torch.float64), 1, torch.zeros(4), torch.zeros(4))
+
+
+def test_noalloc_forward_rejects_oversized_problems_before_any_device_call():
+    lib = _lib.load()
+    g = _lib.GeometryArg(synth.parallel_geometry(synth.fibonacci_directions(2), 3, 3))
+    fake = ctypes.c_void_p(256)
+    # (400 + 8)^3 padded floats exceed the 96 MiB static scratch
+    assert lib.ss_project_noalloc(0, 3, fake, _lib.dims_arg((400, 400, 400)), g.ref(), fake, None) == _lib.SS_EINVAL
+    assert "static scratch" in _lib.last_error()
+    assert lib.ss_project_noalloc(0, 4, fake, _lib.dims_arg((8, 8, 8)), g.ref(), fake, None) == _lib.SS_EINVAL
+    assert lib.ss_project_noalloc(0, 3, None, _lib.dims_arg((8, 8, 8)), g.ref(), fake, None) == _lib.SS_EINVAL
