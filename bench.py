@@ -80,20 +80,47 @@ TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch,
 }
 
 
-def measured_traffic(kernels, degree: int, workload: str):
-    """HBM bytes of one launch of the named kernels (summed), or None when
-    they were not measured for this workload and these sources."""
+# L2 -> L1 fill bytes per launch on cone_256: rocprofv3 TCP_TCC_READ_REQ_sum
+# times 128 bytes, the request size a plain device copy shows (1 GiB read in
+# 8,388,608 requests); same source check as the HBM bytes.  The L2 peak is
+# derived from the unit counts: 8 XCDs x 16 channels x 128 bytes per clock
+# at 2.4 GHz; the best L2-read rate measured by peaks_probe.hip is below it.
+L2_FILL_BYTES = {}
+PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
+MEASURED_L2_READ_TBS = 28.4
+
+
+def _sources_match() -> bool:
     import hashlib
 
-    if workload != "cone_256" or any((k, degree) not in TRAFFIC_BYTES for k in kernels):
-        return None
     h = hashlib.sha256()
     for f in QUAD_SOURCES:
         with open(os.path.join(ROOT, "paper_2511_11078_amd", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != TRAFFIC_SHA256:
+    return h.hexdigest() == TRAFFIC_SHA256
+
+
+def measured_traffic(kernels, degree: int, workload: str):
+    """HBM bytes of one launch of the named kernels (summed), or None when
+    they were not measured for this workload and these sources."""
+    if workload != "cone_256" or any((k, degree) not in TRAFFIC_BYTES for k in kernels):
+        return None
+    if not _sources_match():
         return None
     return float(sum(sum(TRAFFIC_BYTES[(k, degree)]) for k in kernels))
+
+
+def measured_l2(kernels, degree: int, workload: str, ms: float):
+    """L2 -> L1 fill rate of one launch of the named kernels against the L2
+    peak, or None when not measured for this workload and these sources."""
+    if workload != "cone_256" or any((k, degree) not in L2_FILL_BYTES for k in kernels):
+        return None
+    if not _sources_match():
+        return None
+    b = float(sum(L2_FILL_BYTES[(k, degree)] for k in kernels))
+    ach = b / (ms / 1e3) / 1e12
+    return {"bytes": b, "achieved": ach, "peak": PEAK_L2_TBS, "unit": "TB/s", "frac": ach / PEAK_L2_TBS,
+            "frac_of_measured_l2_read": ach / MEASURED_L2_READ_TBS}
 
 
 # FP32 flops of the blending weights of one axis at one node (cell_weights):
@@ -349,17 +376,26 @@ def main():
                     ach = fl / (ms / 1e3) / 1e12
                     knames = [part.strip().split("<")[0] for part in name.split(" (")[0].split("+")]
                     pp = total_pairs * pair_flops(n, segs_per_pair) / (ms / 1e3) / 1e12
-                    ks.append({"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
-                               "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                               "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit,
-                               "traffic": measured_traffic(knames, n, wl.name),
-                               "per_pair_count": {
-                                   "flop_per_pair": pair_flops(n, segs_per_pair),
-                                   "pairs_per_line": pairs_per_ray, "achieved": pp,
-                                   "frac": pp / PEAK_FP32_VECTOR_TFLOPS,
-                                   "note": "exact footprint counted per (line, basis) pair; the kernels share "
-                                           "each knot cell's nodes among its bases, so this count exceeds "
-                                           "the work executed"}})
+                    entry = {"kernel": name, "ms": ms, "bound": "alu", "achieved": ach,
+                             "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                             "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "work": unit}
+                    l2 = measured_l2(knames, n, wl.name, ms)
+                    if l2 is not None and l2["frac"] > entry["frac"]:
+                        # the cheap footprint leaves the walk bound by L2 -> L1 fills
+                        entry["alu"] = {k: entry[k] for k in ("achieved", "peak", "unit", "frac", "work")}
+                        entry.update(bound="l2", achieved=l2["achieved"], peak=l2["peak"], unit=l2["unit"],
+                                     frac=l2["frac"], work=f"{l2['bytes'] / 1e9:.0f} GB of L2 -> L1 fills per "
+                                                           f"launch (TCP_TCC_READ_REQ x 128 bytes)")
+                    entry["l2"] = l2
+                    entry["traffic"] = measured_traffic(knames, n, wl.name)
+                    entry["per_pair_count"] = {
+                        "flop_per_pair": pair_flops(n, segs_per_pair),
+                        "pairs_per_line": pairs_per_ray, "achieved": pp,
+                        "frac": pp / PEAK_FP32_VECTOR_TFLOPS,
+                        "note": "exact footprint counted per (line, basis) pair; the kernels share "
+                                "each knot cell's nodes among its bases, so this count exceeds "
+                                "the work executed"}
+                    ks.append(entry)
             elif form == "pair":
                 fl = total_pairs * pair_flops(n, segs_per_pair)
                 for name, ms in ((f"project_pair_kernel<{n}>", fwd_ms), (f"backproject_pair_kernel<{n}>", adj_ms)):
@@ -383,8 +419,9 @@ def main():
                                        f"{pairs_per_ray:.0f} pairs/line",
                                "mfma": {"achieved": mf, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                                         "frac": mf / PEAK_BF16_MFMA_TFLOPS,
-                                        "work": f"{MLP_FLOPS_PER_PAIR:.0f} flop per pair (hidden layers "
-                                                f"executed twice: two BF16 terms per activation)"}})
+                                        "work": f"{MLP_FLOPS_PER_PAIR:.0f} algorithmic flop per pair; the "
+                                                f"kernel runs each hidden layer's product twice (two BF16 "
+                                                f"terms per activation)"}})
             return ks
 
         kernels = form_kernels(main_form, r0["fwd_ms"], r0["adj_ms"])

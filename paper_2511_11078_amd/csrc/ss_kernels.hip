@@ -498,17 +498,35 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                     synced = true;
                     const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
                     const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
-                    for (int jj = j0; jj <= j1; ++jj)
-                        for (int ii = i0; ii <= i1; ++ii) {
-                            if (count == HITQ_CAP) {  // queue full: integrate its oldest entry now
-                                integrate_hit<n>(rays[hitq[qhead]], lo, acc);
-                                qhead = (qhead + 256) & QMASK;
-                                --count;
-                                nolder = max(nolder - 1, 0);
-                            }
-                            hitq[(qhead + 256 * count) & QMASK] = (unsigned short)(tb + (jj - cj0) * cw + (ii - ci0));
-                            ++count;
+                    const int ni = i1 - i0 + 1, nc = (j1 >= j0 && ni > 0) ? (j1 - j0 + 1) * ni : 0;
+                    if (count + nc <= HITQ_CAP) {
+                        // room for every candidate: one flat loop in the same
+                        // (row, column) order, no overflow test per entry
+                        int e = tb + (j0 - cj0) * cw + (i0 - ci0);  // table entry of the first candidate
+                        int slot = qhead + 256 * count;
+                        for (int k = 0, ii = 0; k < nc; ++k) {
+                            hitq[slot & QMASK] = (unsigned short)e;
+                            slot += 256;
+                            ++ii;
+                            const bool wrap = ii == ni;
+                            e += wrap ? cw - ni + 1 : 1;
+                            ii = wrap ? 0 : ii;
                         }
+                        count += nc;
+                    } else {
+                        for (int jj = j0; jj <= j1; ++jj)
+                            for (int ii = i0; ii <= i1; ++ii) {
+                                if (count == HITQ_CAP) {  // queue full: integrate its oldest entry now
+                                    integrate_hit<n>(rays[hitq[qhead]], lo, acc);
+                                    qhead = (qhead + 256) & QMASK;
+                                    --count;
+                                    nolder = max(nolder - 1, 0);
+                                }
+                                hitq[(qhead + 256 * count) & QMASK] =
+                                    (unsigned short)(tb + (jj - cj0) * cw + (ii - ci0));
+                                ++count;
+                            }
+                    }
                     used += cn;
                 }
             }

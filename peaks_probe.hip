@@ -39,19 +39,30 @@ __global__ void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__
 // and every access is served by the level of the hierarchy that holds the
 // buffer (L2 when it fits an XCD's 4 MB L2, the last-level cache when it
 // fits its 256 MB).  The sum keeps the loads alive.
+template <int U>
 __global__ void __launch_bounds__(256) read_kernel(const float4 *__restrict__ src, long n, int reps,
                                                    float *__restrict__ out) {
-    float a = 0.0f;
+    float a[U];
+    for (int u = 0; u < U; ++u) a[u] = 0.0f;
     const long start = ((long)blockIdx.x * 7919) % n;
+    const long b = blockDim.x;
     for (int r = 0; r < reps; ++r) {
-        for (long i = threadIdx.x; i < n; i += blockDim.x) {
-            long k = start + i;
-            if (k >= n) k -= n;
-            const float4 v = src[k];
-            a += v.x + v.y + v.z + v.w;
+        // U independent loads in flight per thread
+        for (long i = threadIdx.x; i + (U - 1) * b < n; i += U * b) {
+            float4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                long k = start + i + u * b;
+                k -= k >= n ? n : 0;
+                v[u] = src[k];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] += v[u].x + v[u].y + v[u].z + v[u].w;
         }
     }
-    out[blockIdx.x * blockDim.x + threadIdx.x] = a;
+    float t = 0.0f;
+    for (int u = 0; u < U; ++u) t += a[u];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
 constexpr int CHAINS = 16;
@@ -169,7 +180,7 @@ int main() {
     // last-level cache, not the L2); one warm-up pass brings the buffer in
     {
         float *rout = nullptr;
-        const int rblocks = cus * 4;
+        const int rblocks = cus * 8;
         CHECK(hipMalloc(&rout, sizeof(float) * rblocks * 256));
         for (long mib : {2L, 128L}) {
             const long rb = mib << 20, rn = rb / 16;
@@ -178,11 +189,13 @@ int main() {
             CHECK(hipMemset(buf, 0, rb));
             const int reps = mib <= 2 ? 8 : 1;
             const int nblk = rblocks;
-            read_kernel<<<nblk, 256>>>(buf, rn, 1, rout);
-            const float tr = best_ms([&] { read_kernel<<<nblk, 256>>>(buf, rn, reps, rout); });
+            read_kernel<4><<<nblk, 256>>>(buf, rn, 1, rout);
+            const float t4 = best_ms([&] { read_kernel<4><<<nblk, 256>>>(buf, rn, reps, rout); });
+            const float t8 = best_ms([&] { read_kernel<8><<<nblk, 256>>>(buf, rn, reps, rout); });
             const double moved = (double)nblk * reps * rb;
-            std::printf("read %ld MiB buffer, %d blocks x %d passes: %.3f ms, %.0f GB/s\n", mib, nblk, reps, tr,
-                        moved / (tr * 1e-3) / 1e9);
+            std::printf("read %ld MiB buffer, %d blocks x %d passes: 4 loads in flight %.3f ms, %.0f GB/s; "
+                        "8 in flight %.3f ms, %.0f GB/s\n", mib, nblk, reps, t4, moved / (t4 * 1e-3) / 1e9, t8,
+                        moved / (t8 * 1e-3) / 1e9);
             CHECK(hipFree(buf));
         }
         CHECK(hipFree(rout));

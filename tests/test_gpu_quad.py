@@ -149,7 +149,7 @@ def test_minimal_sizes_both_directions(ctxs, n, case):
         assert np.abs(got).max() == 0 and np.abs(gb).max() == 0
 
 
-@pytest.mark.parametrize("n", [0, 2, 3])
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
 def test_backproject_all_coefficients(ctxs, n, kind):
     say(f"backproject {kind} n={n}")
