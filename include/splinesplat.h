@@ -137,10 +137,14 @@ ss_status ss_project(ss_ctx *ctx, const float *d_coeffs, const int64_t dims[3],
  * overwritten.  Same layouts and errors as ss_project.
  * With SS_FORM_QUAD_FP32 the context keeps a device table of (degree+1)^3
  * floats per knot cell of the support-padded volume (4.45 GB for 256^3,
- * degree 3), allocated on the first call that needs it and at most 8 GiB
- * (larger volumes are processed in z-chunks); growing it waits for the
- * device.  Calls on one context must not overlap in time (they share the
- * table).  Additional error: SS_ENOMEM when the table cannot be allocated. */
+ * 35.6 GB for 512^3, degree 3), allocated on the first call that needs it
+ * and at most the context's scratch limit (64 GiB unless set with
+ * ss_set_scratch_limit; a larger table is processed in z-chunks of cell
+ * layers, recomputing `degree` layers at each chunk boundary; the result
+ * equals one pass up to FP32 rounding, as the cell bricks align to each
+ * chunk's first layer); growing it waits for the device.  Calls on one
+ * context must not overlap in time (they share the table).  Additional
+ * error: SS_ENOMEM when the table cannot be allocated. */
 ss_status ss_backproject(ss_ctx *ctx, const float *d_sino, const ss_geometry *geom,
                          const int64_t dims[3], float *d_coeffs, void *hip_stream);
 
@@ -162,6 +166,15 @@ ss_status ss_backproject(ss_ctx *ctx, const float *d_sino, const ss_geometry *ge
 #define SS_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
 ss_status ss_project_noalloc(int device, int degree, const float *d_coeffs, const int64_t dims[3],
                              const ss_geometry *geom, float *d_sino, void *hip_stream);
+
+/* Largest knot-cell table (bytes) the quadrature adjoint of this context
+ * may allocate; 0 restores the default of 64 GiB.  Tables that would be
+ * larger are processed in z-chunks (never fewer than 4 (degree+1) cell
+ * layers per chunk, whatever the limit).  For callers that share the GPU's
+ * memory with other work: they trade memory for recomputed layers.  A
+ * scratch buffer already above the new limit is released (after waiting for
+ * the device).  Errors: SS_EINVAL (ctx NULL), SS_EDEVICE. */
+ss_status ss_set_scratch_limit(ss_ctx *ctx, size_t bytes);
 
 /* Evaluate the context's footprint P phi(w, x) = int phi(x + t w) dt (the
  * contribution of eq. (4)) for `count` pairs: d_dirs FP32 [count][3] (unit

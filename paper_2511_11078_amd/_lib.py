@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_EDEVICE", 4: 
 
 EXPORTED = ["ss_create", "ss_destroy", "ss_project", "ss_backproject", "ss_footprint", "ss_dot_f64",
             "ss_cgls_scalars", "ss_axpy", "ss_xpay", "ss_validate_problem", "ss_last_error", "ss_query",
-            "ss_abi_version", "ss_project_noalloc"]
+            "ss_abi_version", "ss_project_noalloc", "ss_set_scratch_limit"]
 
 
 class SSError(RuntimeError):
@@ -57,6 +57,7 @@ def load():
     lib.ss_backproject.argtypes = [P, P, ctypes.POINTER(ss_geometry), P, P, P]
     lib.ss_project_noalloc.argtypes = [I, I, P, P, ctypes.POINTER(ss_geometry), P, P]
     lib.ss_footprint.argtypes = [P, P, P, L, P, P]
+    lib.ss_set_scratch_limit.argtypes = [P, ctypes.c_size_t]
     lib.ss_dot_f64.argtypes = [P, P, P, L, P, P]
     lib.ss_cgls_scalars.argtypes = [P, P, P, P, P]
     lib.ss_axpy.argtypes = [P, P, I, P, P, L, P]

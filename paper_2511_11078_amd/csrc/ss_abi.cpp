@@ -6,6 +6,7 @@
 // (degree, form).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -28,6 +29,7 @@ struct ss_ctx {
     void *d_mlp = nullptr;          // network weights in kernel layout
     float *d_cells = nullptr;       // quadrature scratch: padded coefficients (forward), knot-cell table (adjoint)
     int64_t cells_cap = 0;          // floats
+    int64_t cell_limit = ss::CELL_SCRATCH_DEFAULT_FLOATS;  // largest knot-cell table (floats)
 };
 
 namespace ss {
@@ -320,9 +322,10 @@ static ss_status run_transform(ss_ctx *ctx, bool forward, const float *in, const
         a.sino_in = in;
         a.coeffs_out = out;
         if (ctx->form == SS_FORM_QUAD_FP32) {
-            if (ss_status s = ensure_cells(ctx, ss::backproject_quad_scratch_floats(ctx->degree, a.N))) return s;
+            const int64_t need = ss::backproject_quad_scratch_floats(ctx->degree, a.N, ctx->cell_limit);
+            if (ss_status s = ensure_cells(ctx, need)) return s;
             a.scratch = ctx->d_cells;
-            a.scratch_floats = ctx->cells_cap;
+            a.scratch_floats = need;  // the chunking follows the limit, not the buffer's size
         }
         e = ctx->form == SS_FORM_QUAD_FP32   ? ss::launch_backproject_quad(ctx->degree, a, st)
             : ctx->form == SS_FORM_MLP_BF16  ? ss::launch_backproject_mlp(ctx->degree, a, st)
@@ -382,6 +385,24 @@ ss_status ss_project_noalloc(int device, int degree, const float *d_coeffs, cons
     a.scratch = base + geom_floats;
     a.scratch_floats = ss::STATIC_SCRATCH_FLOATS - geom_floats;
     if ((e = ss::launch_project_quad(degree, a, st)) != hipSuccess) return hip_fail(e, "project launch");
+    return SS_OK;
+}
+
+ss_status ss_set_scratch_limit(ss_ctx *ctx, size_t bytes) {
+    if (ss_status s = check_ctx(ctx)) return s;
+    const int64_t floats = bytes == 0 ? ss::CELL_SCRATCH_DEFAULT_FLOATS
+                                      : (int64_t)std::min<size_t>(bytes / sizeof(float), (size_t)1 << 40);
+    ctx->cell_limit = floats;
+    if (ctx->d_cells && ctx->cells_cap > floats) {
+        // release a buffer above the new limit (enqueued work may still use it)
+        DeviceGuard guard(ctx->device);
+        if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
+        hipError_t e;
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->d_cells);
+        ctx->d_cells = nullptr;
+        ctx->cells_cap = 0;
+    }
     return SS_OK;
 }
 

@@ -737,14 +737,14 @@ int64_t project_quad_scratch_floats(int degree, const int N[3]) {
     return (N[0] + 2 * P) * (N[1] + 2 * P) * (N[2] + 2 * P);
 }
 
-int64_t backproject_quad_scratch_floats(int degree, const int N[3]) {
+int64_t backproject_quad_scratch_floats(int degree, const int N[3], int64_t limit) {
     const int64_t nb = degree + 1;
     const int64_t layer = nb * nb * nb * (int64_t)(N[0] + degree) * (N[1] + degree);
     const int64_t full = layer * (N[2] + degree);
     // at least 4 (n + 1) layers per chunk, so that chunking re-does at most
     // a quarter of the cell layers
     const int64_t floor_layers = std::min<int64_t>(N[2] + degree, 4 * nb);
-    return std::min(full, std::max(CELL_SCRATCH_FLOATS, layer * floor_layers));
+    return std::min(full, std::max(limit, layer * floor_layers));
 }
 
 template <int n>

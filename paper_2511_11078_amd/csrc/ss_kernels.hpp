@@ -38,11 +38,13 @@ struct LaunchArgs {
     int64_t scratch_floats;
 };
 
-// Largest knot-cell table of the quadrature adjoint: 2^31 floats (8 GiB);
-// larger volumes are processed in z-chunks of cell layers.
-constexpr int64_t CELL_SCRATCH_FLOATS = (int64_t)1 << 31;
-// Table size the quadrature adjoint uses for a volume of N[0] x N[1] x N[2].
-int64_t backproject_quad_scratch_floats(int degree, const int N[3]);
+// Default largest knot-cell table of the quadrature adjoint: 2^34 floats
+// (64 GiB; 256^3 needs 4.45 GB, 512^3 35.6 GB); larger tables are processed
+// in z-chunks of cell layers.  A context may set another limit.
+constexpr int64_t CELL_SCRATCH_DEFAULT_FLOATS = (int64_t)1 << 34;
+// Table size the quadrature adjoint uses for a volume of N[0] x N[1] x N[2]
+// under a limit of `limit` floats (never below 4 (n+1) cell layers).
+int64_t backproject_quad_scratch_floats(int degree, const int N[3], int64_t limit);
 // Zero-padded copy of the coefficients the quadrature forward walks.
 #define FWD_PAD(n) ((n) + 1)
 int64_t project_quad_scratch_floats(int degree, const int N[3]);

@@ -72,6 +72,11 @@ class Context:
         self._h = h
         self._lib = lib
 
+    def set_scratch_limit(self, nbytes: int):
+        """Largest knot-cell table the quadrature adjoint may allocate; larger
+        tables are processed in z-chunks (ss_set_scratch_limit)."""
+        _lib.check(self._lib.ss_set_scratch_limit(self._h, int(nbytes)))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.ss_destroy(self._h)

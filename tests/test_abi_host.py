@@ -110,6 +110,7 @@ def test_null_context_is_rejected():
     assert lib.ss_axpy(None, P, 1, P, P, 4, None) == _lib.SS_EINVAL
     assert lib.ss_xpay(None, P, P, P, 4, None) == _lib.SS_EINVAL
     assert lib.ss_query(None, None, None, None) == _lib.SS_EINVAL
+    assert lib.ss_set_scratch_limit(None, 1 << 20) == _lib.SS_EINVAL
     assert lib.ss_destroy(None) == _lib.SS_OK
     assert "NULL" in _lib.last_error() or "context" in _lib.last_error()
 

@@ -167,6 +167,36 @@ def test_backproject_all_coefficients(ctxs, n, kind):
     assert e <= (TOL if n > 0 else 1e-4)
 
 
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_backproject_z_chunks_match_one_pass(n):
+    """A scratch limit below the knot-cell table splits the adjoint into
+    z-chunks of 4 (n+1) cell layers (the floor) that overlap by n layers:
+    the result matches the one-pass adjoint to FP32 rounding (the cell
+    bricks align to each chunk's first layer, so line set-ups round
+    differently; a lost or doubled layer would differ by O(1)), and the
+    oracle on every coefficient.  A ragged last chunk (the layer count is not
+    a multiple of the chunk step) and a default limit restored afterwards."""
+    say(f"backproject z-chunks n={n}")
+    dims = (23, 19, 61)
+    geom = synth.cone_circular_geometry(6, 29, 33, src_radius=80.0, src_det=120.0, pitch=1.7, angle0=0.4)
+    y = np.random.default_rng(250 + n).standard_normal((geom.n_views, geom.det_rows, geom.det_cols)).astype(np.float32)
+    one = Context(n, "quad", 0)
+    chunked = Context(n, "quad", 0)
+    chunked.set_scratch_limit(1)
+    b1 = to_np(one.backproject(to_gpu(y), geom, dims))
+    bc = to_np(chunked.backproject(to_gpu(y), geom, dims))
+    e_pass = rel_l2(bc, b1)
+    e_oracle = rel_l2(bc, oracle.backproject_subset(y, geom, dims, n))
+    chunked.set_scratch_limit(0)
+    bd = to_np(chunked.backproject(to_gpu(y), geom, dims))
+    say(f"  chunked vs one pass {e_pass:.2e}, vs oracle {e_oracle:.2e}, default again {rel_l2(bd, b1):.1e}")
+    assert e_pass <= 2e-6
+    assert e_oracle <= (TOL if n > 0 else 1e-4)
+    assert np.array_equal(bd, b1)
+    one.close()
+    chunked.close()
+
+
 @pytest.mark.parametrize("case", ["cone_fine_pitch", "parallel_wide_rows"])
 def test_backproject_large_shadows(ctxs, case):
     """Detector pixels much smaller than a knot cell: a brick's shadow holds
