@@ -67,16 +67,16 @@ MLP_TRANS_PER_PAIR = 2 * 4 * 64   # SiLU of 4 x 64 hidden units: one exp and one
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "af9b9f6a3b6a81a63c1ada38f76e2b93262ee13f581b01b046d4ecb9d5ae7717"
+TRAFFIC_SHA256 = "3b280a7dd9a439142003123b36e4d48ed07591e493feb641139a54c9a90e0d17"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36893 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1530252 * 1024, 1.0 * 228933 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3163064 * 1024, 1.0 * 5672038 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2471425 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 3): (2.0 * 1530043 * 1024, 1.0 * 228711 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3020361 * 1024, 1.0 * 5435998 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2469549 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36895 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1072402 * 1024, 1.0 * 254743 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1263741 * 1024, 1.0 * 67092 * 1024),
-    ("cells_to_coeffs_kernel", 0): (2.0 * 32781 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 0): (2.0 * 1069215 * 1024, 1.0 * 254652 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1250446 * 1024, 1.0 * 67074 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32787 * 1024, 1.0 * 65536 * 1024),
 }
 
 
@@ -87,12 +87,12 @@ TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch,
 # at 2.4 GHz; the best L2-read rate measured by peaks_probe.hip is below it.
 L2_FILL_BYTES = {  # (kernel, degree) -> bytes per launch, cone_256
     ("pad_volume_kernel", 3): 128.0 * 589824,
-    ("project_kernel", 3): 128.0 * 23821059355,
-    ("backproject_cells_kernel", 3): 128.0 * 212424917,
-    ("cells_to_coeffs_kernel", 3): 128.0 * 44637426,
+    ("project_kernel", 3): 128.0 * 23811369747,
+    ("backproject_cells_kernel", 3): 128.0 * 210756872,
+    ("cells_to_coeffs_kernel", 3): 128.0 * 45826707,
     ("pad_volume_kernel", 0): 128.0 * 589824,
-    ("project_kernel", 0): 128.0 * 5703653759,
-    ("backproject_cells_kernel", 0): 128.0 * 194940320,
+    ("project_kernel", 0): 128.0 * 5703180801,
+    ("backproject_cells_kernel", 0): 128.0 * 194943899,
     ("cells_to_coeffs_kernel", 0): 128.0 * 524288,
 }
 PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12

@@ -222,16 +222,20 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
 // ---------------------------------------------------------------------------
 constexpr int GX = 8, GY = 8, GZ = 4;
 constexpr int NCORNER = (GX + 1) * (GY + 1) * (GZ + 1);
+constexpr int HITQ_CAP = 32;                    // queued candidates per thread (a ring)
 // Line table (two halves) and occupancy per degree: the cubic kernel's
 // registers allow three waves per SIMD, so its table takes what LDS leaves
-// for three blocks per CU; lower degrees fit four waves and a smaller table.
+// for three blocks per CU beside the candidate queues and two corner tables,
+// counting 160 KiB in 2 KiB units (three blocks of 54,232 bytes did not fit
+// on a CU); lower degrees fit four waves and a smaller table.
 template <int n> struct CellGather {
     static constexpr int waves = n == 3 ? 3 : 4;          // waves per SIMD: blocks per CU
-    static constexpr int cap = n == 3 ? 832 : 512;        // lines in the LDS table
+    static constexpr int lds = (160 * 1024 / waves) / 2048 * 2048;
+    static constexpr int fixed = HITQ_CAP * 256 * 2 + 2 * NCORNER * 8 + 16;
+    static constexpr int cap = (lds - fixed) / 40 / 16 * 16;  // lines in the LDS table (40 bytes each)
     static constexpr int half = cap / 2;
     static constexpr int views_per_half = n == 3 ? 5 : 3;
 };
-constexpr int HITQ_CAP = 32;                    // queued candidates per thread (a ring)
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
 struct __attribute__((aligned(8))) CellRay {  // 40 bytes
@@ -369,9 +373,11 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
     constexpr int CRAY_HALF = CellGather<n>::half, VIEWS_PER_HALF = CellGather<n>::views_per_half;
+    static_assert(sizeof(CellRay) == 40, "line record size assumed by the LDS budget");
     __shared__ CellRay rays[CellGather<n>::cap];
     __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of candidate table indices
-    __shared__ float2 corner[NCORNER];
+    __shared__ float2 corner[2][NCORNER];            // view v's corner table in [v & 1]
+    __shared__ int badview[2];  // v + 1 in [v & 1] when a corner of view v is on or behind the source plane
     const int M0 = N0 + n, M1 = N1 + n;  // cells per row / column
     const int nbx = (M0 + GX - 1) / GX, nby = (M1 + GY - 1) / GY, nbz = (L + GZ - 1) / GZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -401,18 +407,18 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     // other half
     constexpr int QMASK = HITQ_CAP * 256 - 1;
     int qhead = tid, count = 0, nolder = 0;
-    bool synced = true;        // block-uniform: every thread is past its reads of the corner table
 
-    for (int v = 0; v < V; ++v) {
-        const float *e = geom + 12 * v;
+    // Detector position (pixel units) of every lattice corner of the brick
+    // for view v, into corner[v & 1]; a corner on or behind the source plane
+    // (no bounded shadow) stores v + 1 into badview[v & 1] (every writer the
+    // same value, so no reset is needed).  View v + 1's table is written
+    // while view v's lines are set up, so that one barrier per view orders
+    // both: each view's phase ends with at least one barrier, table [v & 1]
+    // and flag [v & 1] are read in phase v and rewritten in phase v + 1.
+    auto project_corners = [&](int v) {
         LocalProj lp;  // the same in every thread
         make_localproj(vps[v], centre, lp);
-        // the previous view's corner table may still be read unless a
-        // segment barrier has passed since
-        if (!synced) __syncthreads();
-        synced = false;
-        // detector position (pixel units) of every lattice corner of the brick
-        bool bad = false;  // a corner on or behind the source plane: no bounded shadow
+        bool bad = false;
 #pragma unroll
         for (int it = 0; it < (NCORNER + 255) / 256; ++it) {  // independent iterations
             const int t = tid + 256 * it;
@@ -422,10 +428,20 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                 float cc = 0.0f, rr = 0.0f;
                 const bool ok = local_to_detector(lp, d, cc, rr);
                 bad = bad || !ok;
-                corner[t] = make_float2(cc + oc, rr + orow);
+                corner[v & 1][t] = make_float2(cc + oc, rr + orow);
             }
         }
-        const bool anybad = __syncthreads_or(bad);
+        if (bad) badview[v & 1] = v + 1;
+    };
+    if (tid < 2) badview[tid] = -1;
+    __syncthreads();
+    if (V > 0) project_corners(0);
+    __syncthreads();
+
+    for (int v = 0; v < V; ++v) {
+        const float *e = geom + 12 * v;
+        const float2 *cornerv = corner[v & 1];
+        const bool anybad = badview[v & 1] == v + 1;
         // the brick's pixel rectangle (from its eight corners, the same for
         // every thread) and this cell's candidate pixels (from its own)
         int bi0, bi1, bj0, bj1;
@@ -435,14 +451,16 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
             if (mine) { mi0 = 0; mi1 = C - 1; mj0 = 0; mj1 = R - 1; }
         } else {
             float bc0, bc1, br0, br1;
-            corner_bounds(corner, GX, GY, GZ, 0, 0, 0, bc0, bc1, br0, br1);
+            corner_bounds(cornerv, GX, GY, GZ, 0, 0, 0, bc0, bc1, br0, br1);
             pixel_rect(bc0, bc1, br0, br1, R, C, bi0, bi1, bj0, bj1);
             if (mine) {
                 float c0, c1, r0, r1;
-                corner_bounds(corner, 1, 1, 1, tx, ty, tz, c0, c1, r0, r1);
+                corner_bounds(cornerv, 1, 1, 1, tx, ty, tz, c0, c1, r0, r1);
                 pixel_rect(c0, c1, r0, r1, R, C, mi0, mi1, mj0, mj1);
             }
         }
+        if (v + 1 < V) project_corners(v + 1);
+        bool barrier = false;  // block-uniform: a barrier has passed in this view's phase
         // the view's lines go into the current half of the table in segments
         // of whole rows (of columns, for a row wider than a half); this cell's
         // candidates are queued, and integrated before their half is refilled
@@ -495,7 +513,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                                      y[((int64_t)v * R + jj) * C + ii]);
                     }
                     __syncthreads();
-                    synced = true;
+                    barrier = true;
                     const int j0 = max(mj0, cj0), j1 = min(mj1, cj1);
                     const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
                     const int ni = i1 - i0 + 1, nc = (j1 >= j0 && ni > 0) ? (j1 - j0 + 1) * ni : 0;
@@ -532,6 +550,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
             }
             ++nviews;
         }
+        if (!barrier) __syncthreads();
     }
     int idx = hitq[qhead];
     for (int k = 0; k < count; ++k) {
