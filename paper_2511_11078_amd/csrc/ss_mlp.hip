@@ -214,18 +214,14 @@ __device__ __forceinline__ float mlp_tile(const MlpImage &W, float f0, float f1,
     return part + W.bout;
 }
 
-// Both tiles of a wave: each lane gets the value of its own pair.  With
-// INTERLEAVE the two independent tiles are left to the scheduler, which
-// interleaves one tile's matrix-core work with the other's SiLU (faster for
-// the forward: 24 views of cone_256, 1,263 against 1,485 ms); otherwise a
-// scheduling barrier keeps them apart, which halves the live activations
-// (the adjoint, which holds its line table and candidate state besides,
-// then spills 10 registers instead of 135: 1,636 against 1,807 ms).
-template <bool INTERLEAVE>
+// Both tiles of a wave: each lane gets the value of its own pair.  The two
+// independent tiles are left to the scheduler, which interleaves one tile's
+// matrix-core work with the other's SiLU (24 views of cone_256: forward
+// 1,263 against 1,485 ms with a scheduling barrier between the tiles; the
+// adjoint, whose candidate state then spills, 1,237 against 1,394 ms).
 __device__ __forceinline__ float mlp_wave(const MlpImage &W, const float f[5]) {
     const int lane = threadIdx.x & 63;
     const float ra = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 0);
-    if constexpr (!INTERLEAVE) __builtin_amdgcn_sched_barrier(0);
     const float rb = mlp_tile(W, f[0], f[1], f[2], f[3], f[4], 32);
     return lane < 32 ? ra : rb;
 }
@@ -415,7 +411,7 @@ __device__ __forceinline__ void project_walk(const float *__restrict__ c, int N0
             f[2] = F.wf[2];
             f[3] = fmaf(Ui1, u1, Ui2 * u2);
             f[4] = fmaf(Vi1, u1, Vi2 * u2);
-            fp = mlp_wave<true>(*Wt, f);
+            fp = mlp_wave(*Wt, f);
         }
         if (have) acc = fmaf(c[idx], fp, acc);
     }
@@ -467,6 +463,15 @@ struct RayRecM {     // 80 bytes
     float pad;
 };
 
+// The network adjoint's pairs waiting to be evaluated, a ring of 128 per
+// wave: the five features and y of each pair and its owning thread.  A wave
+// appends only its own lanes' pairs, so each ring is used by one wave.
+constexpr int PBUF = 128;
+struct PairBuf {
+    float v[6][PBUF];
+    int owner[PBUF];
+};
+
 template <int n>
 __device__ __forceinline__ void fill_ray_m(RayRecM &rec, const float *__restrict__ e, int kind, int R, int C,
                                            int j, int i, const double centre[3], float yval) {
@@ -488,16 +493,21 @@ __device__ __forceinline__ void fill_ray_m(RayRecM &rec, const float *__restrict
 }
 
 // Coefficient-brick gather: each thread owns one coefficient and sums, view
-// by view, y_m times the footprint over the pixels of its support's shadow.
-// The footprint comes from the network (EXACT = false, 64 pairs per round
-// on the matrix cores) or from the exact piecewise Gauss-Legendre integral
-// (EXACT = true, each lane on its own).
+// by view, y_m times the footprint over the pixels of its support's shadow;
+// each lane finds its own pairs (the pixels whose line meets its support).
+// The exact form (EXACT = true) evaluates the piecewise Gauss-Legendre
+// integral of every lane's next pair in the same round.  The network form
+// appends the pairs to its wave's ring and, whenever 64 are buffered,
+// evaluates them together on the matrix cores, one pair per lane, adding y
+// times the footprint to the owners' sums in LDS (atomic adds within the
+// wave, since owner and evaluating lane differ): every round is full, and
+// pairs carry over from one chunk or view to the next.
 template <int n, bool EXACT>
 __device__ __forceinline__ void backproject_gather(const float *__restrict__ y, int N0, int N1, int N2,
                                                    const float *__restrict__ geom, const ViewProj *__restrict__ vps,
                                                    int kind, int V, int R, int C, const MlpImage *Wt,
                                                    RayRecM *rays, ViewProj &vp, LocalProj &lp, int *sbox,
-                                                   float *__restrict__ c) {
+                                                   PairBuf *pbuf, float *accw, float *__restrict__ c) {
     constexpr float hf = Degree<n>::h;
     const int nbx = (N0 + MBX - 1) / MBX, nby = (N1 + MBY - 1) / MBY, nbz = (N2 + MBZ - 1) / MBZ;
     const int b = xcd_remap(blockIdx.x, nbx * nby * nbz);
@@ -511,7 +521,35 @@ __device__ __forceinline__ void backproject_gather(const float *__restrict__ y, 
                               o[2] + bz * MBZ + 0.5 * (MBZ - 1)};
     const float xq[3] = {(float)(o[0] + k0 - centre[0]), (float)(o[1] + k1 - centre[1]),
                          (float)(o[2] + k2 - centre[2])};
-    float acc = 0.0f;
+    float acc = 0.0f;                 // exact form: this coefficient's sum
+    const int lane = tid & 63;
+    int head = 0, wcount = 0;         // network form, wave-uniform: oldest buffered pair, how many
+    if constexpr (!EXACT) {
+        PairBuf &B = pbuf[tid >> 6];
+        accw[tid] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            B.v[q][lane] = 0.0f;
+            B.v[q][lane + 64] = 0.0f;
+        }
+        B.owner[lane] = tid;
+        B.owner[lane + 64] = tid;
+    }
+    // network form: evaluate the cnt oldest buffered pairs (wave-uniform
+    // cnt <= 64, every lane of the wave taking part) and add their terms to
+    // the owners' sums
+    auto flush = [&](int cnt) {
+        if constexpr (!EXACT) {
+            const PairBuf &B = pbuf[tid >> 6];
+            const int e = (head + lane) & (PBUF - 1);
+            const float f[5] = {B.v[0][e], B.v[1][e], B.v[2][e], B.v[3][e], B.v[4][e]};
+            const float yv = B.v[5][e];
+            const int own = B.owner[e];
+            const float fp = mlp_wave(*Wt, f);
+            if (lane < cnt)
+                __hip_atomic_fetch_add(&accw[own], yv * fp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
     for (int v = 0; v < V; ++v) {
         const float *e = geom + 12 * v;
         __syncthreads();
@@ -578,51 +616,89 @@ __device__ __forceinline__ void backproject_gather(const float *__restrict__ y, 
                 const int i0 = max(mi0, ci0), i1 = min(mi1, ci1);
                 int jj = j0, ii = i0;
                 bool live = j0 <= j1 && i0 <= i1;
-                while (true) {
-                    bool have = false;
-                    float yv = 0.0f, f3 = 0.0f, f4 = 0.0f, w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
-                    float pu1 = 0.0f, pu2 = 0.0f, iwd = 0.0f;
-                    Slopes PS = make_slopes(0.0f, 0.0f);
-                    while (live && !have) {
-                        const RayRecM &rr = rays[(jj - cj0) * cw + (ii - ci0)];
-                        const int d = rr.d;
-                        const int i1x = d == 0 ? 1 : 0, i2x = d == 2 ? 1 : 2;
-                        const float t = pick3(xq, d) - pick3(rr.a, d);
-                        const float u1 = fmaf(t, rr.r1, pick3(rr.a, i1x)) - pick3(xq, i1x);
-                        const float u2 = fmaf(t, rr.r2, pick3(rr.a, i2x)) - pick3(xq, i2x);
-                        Slopes S;
-                        S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
-                        if (chord_nonempty<n>(S, u1, u2)) {
-                            have = true;
-                            yv = rr.y;
-                            if constexpr (EXACT) {
+                if constexpr (EXACT) {
+                    // every round each lane with pixels left evaluates its next pair
+                    while (true) {
+                        bool have = false;
+                        float yv = 0.0f, pu1 = 0.0f, pu2 = 0.0f, iwd = 0.0f;
+                        Slopes PS = make_slopes(0.0f, 0.0f);
+                        while (live && !have) {
+                            const RayRecM &rr = rays[(jj - cj0) * cw + (ii - ci0)];
+                            const int d = rr.d;
+                            const int i1x = d == 0 ? 1 : 0, i2x = d == 2 ? 1 : 2;
+                            const float t = pick3(xq, d) - pick3(rr.a, d);
+                            const float u1 = fmaf(t, rr.r1, pick3(rr.a, i1x)) - pick3(xq, i1x);
+                            const float u2 = fmaf(t, rr.r2, pick3(rr.a, i2x)) - pick3(xq, i2x);
+                            Slopes S;
+                            S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
+                            if (chord_nonempty<n>(S, u1, u2)) {
+                                have = true;
+                                yv = rr.y;
                                 pu1 = u1;
                                 pu2 = u2;
                                 PS = S;
                                 iwd = rr.iwd;
-                            } else {
-                                const float x0 = rr.a[0] - xq[0], x1 = rr.a[1] - xq[1], x2 = rr.a[2] - xq[2];
-                                f3 = fmaf(rr.U[0], x0, fmaf(rr.U[1], x1, rr.U[2] * x2));
-                                f4 = fmaf(rr.V[0], x0, fmaf(rr.V[1], x1, rr.V[2] * x2));
-                                w0 = rr.wf[0]; w1 = rr.wf[1]; w2 = rr.wf[2];
                             }
+                            ++ii;
+                            if (ii > i1) { ii = i0; ++jj; }
+                            live = jj <= j1;
                         }
-                        ++ii;
-                        if (ii > i1) { ii = i0; ++jj; }
-                        live = jj <= j1;
+                        if (__ballot(have) == 0) break;
+                        const float fp = have ? footprint_slab<n>(PS, pu1, pu2) * iwd : 0.0f;
+                        if (have) acc = fmaf(yv, fp, acc);
                     }
-                    if (__ballot(have) == 0) break;
-                    float fp;
-                    if constexpr (EXACT) {
-                        fp = have ? footprint_slab<n>(PS, pu1, pu2) * iwd : 0.0f;
-                    } else {
-                        const float f[5] = {w0, w1, w2, f3, f4};
-                        fp = mlp_wave<false>(*Wt, f);
+                } else {
+                    // every round each lane with pixels left finds its next
+                    // pair; the found pairs go into the ring (at most 63 + 64)
+                    while (true) {
+                        bool have = false;
+                        float pv[6];
+                        while (live && !have) {
+                            const RayRecM &rr = rays[(jj - cj0) * cw + (ii - ci0)];
+                            const int d = rr.d;
+                            const int i1x = d == 0 ? 1 : 0, i2x = d == 2 ? 1 : 2;
+                            const float t = pick3(xq, d) - pick3(rr.a, d);
+                            const float u1 = fmaf(t, rr.r1, pick3(rr.a, i1x)) - pick3(xq, i1x);
+                            const float u2 = fmaf(t, rr.r2, pick3(rr.a, i2x)) - pick3(xq, i2x);
+                            Slopes S;
+                            S.r1 = rr.r1; S.r2 = rr.r2; S.ir1 = rr.ir1; S.ir2 = rr.ir2;
+                            if (chord_nonempty<n>(S, u1, u2)) {
+                                have = true;
+                                const float x0 = rr.a[0] - xq[0], x1 = rr.a[1] - xq[1], x2 = rr.a[2] - xq[2];
+                                pv[0] = rr.wf[0]; pv[1] = rr.wf[1]; pv[2] = rr.wf[2];
+                                pv[3] = fmaf(rr.U[0], x0, fmaf(rr.U[1], x1, rr.U[2] * x2));
+                                pv[4] = fmaf(rr.V[0], x0, fmaf(rr.V[1], x1, rr.V[2] * x2));
+                                pv[5] = rr.y;
+                            }
+                            ++ii;
+                            if (ii > i1) { ii = i0; ++jj; }
+                            live = jj <= j1;
+                        }
+                        const uint64_t m = __ballot(have);
+                        if (m == 0) break;  // every lane has exhausted this chunk
+                        if (have) {
+                            PairBuf &B = pbuf[tid >> 6];
+                            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            const int slot = (head + wcount + rank) & (PBUF - 1);
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) B.v[q][slot] = pv[q];
+                            B.owner[slot] = tid;
+                        }
+                        wcount += __popcll(m);
+                        if (wcount >= 64) {
+                            flush(64);
+                            head = (head + 64) & (PBUF - 1);
+                            wcount -= 64;
+                        }
                     }
-                    if (have) acc = fmaf(yv, fp, acc);
                 }
             }
         }
+    }
+    if constexpr (!EXACT) {
+        if (wcount > 0) flush(wcount);
+        acc = accw[tid];  // the wave's atomic adds precede this read (LDS operations of a wave run in order)
     }
     if (mine) c[((int64_t)k2 * N1 + k1) * N0 + k0] = acc;
 }
@@ -638,8 +714,10 @@ __global__ void __launch_bounds__(256, 2) backproject_mlp_kernel(const float *__
     __shared__ ViewProj vp;
     __shared__ LocalProj lp;
     __shared__ int sbox[4];
+    __shared__ PairBuf pbuf[4];  // one ring per wave of the 256-thread block
+    __shared__ float accw[256];
     load_image(Wt, img);
-    backproject_gather<n, false>(y, N0, N1, N2, geom, vps, kind, V, R, C, &Wt, rays, vp, lp, sbox, c);
+    backproject_gather<n, false>(y, N0, N1, N2, geom, vps, kind, V, R, C, &Wt, rays, vp, lp, sbox, pbuf, accw, c);
 }
 
 template <int n>
@@ -651,7 +729,8 @@ __global__ void __launch_bounds__(256) backproject_pair_kernel(const float *__re
     __shared__ ViewProj vp;
     __shared__ LocalProj lp;
     __shared__ int sbox[4];
-    backproject_gather<n, true>(y, N0, N1, N2, geom, vps, kind, V, R, C, nullptr, rays, vp, lp, sbox, c);
+    backproject_gather<n, true>(y, N0, N1, N2, geom, vps, kind, V, R, C, nullptr, rays, vp, lp, sbox, nullptr, nullptr,
+                                c);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +770,7 @@ __global__ void __launch_bounds__(64) footprint_mlp_kernel(const float *__restri
             f[4] = fmaf(F.V[0], xf[0], fmaf(F.V[1], xf[1], F.V[2] * xf[2]));
         }
     }
-    const float fp = mlp_wave<true>(Wt, f);
+    const float fp = mlp_wave(Wt, f);
     if (k < count) out[k] = have ? fp : 0.0f;
 }
 
