@@ -23,8 +23,9 @@
  *     5 -> 4 x 64 (SiLU) -> 1, hidden layers on BF16 matrix cores with FP32
  *     accumulation, gated by the exact line/support intersection test.
  * The adjoint (Sec. 2.3 states that the projection algorithm with minor
- * changes gives a matched adjoint) is an atomic-free gather: each
- * coefficient sums over the detector pixels of its own shadow.
+ * changes gives a matched adjoint) is a gather: each coefficient sums over
+ * the detector pixels of its own shadow and has a single writer (no atomic
+ * operations in device memory; results are deterministic).
  *
  * Conventions shared by every entry point
  *   - Coefficient k = (k1, k2, k3) sits at world position
