@@ -10,9 +10,9 @@ network form from the exact transform (FP64 oracle), in both directions?
 The bound on the latter is the network form's stated 1e-3 for degree 2.
 The degree-1 footprint has creases (beta^1 is only continuous), which a
 smooth SiLU network of this size fits less well: its validation fit is
-7.0e-4 on the training distribution of directions, and on the 32 spherical
+5.3e-4 on the training distribution of directions, and on the 32 spherical
 Fibonacci directions of the parallel test the projections differ from the
-oracle by 1.1e-3 (forward) and 1.5e-3 (adjoint of noise); its bound is
+oracle by 1.0e-3 (forward) and 1.3e-3 (adjoint of noise); its bound is
 2e-3.
 """
 import os
