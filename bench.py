@@ -67,7 +67,7 @@ MLP_TRANS_PER_PAIR = 2 * 4 * 64   # SiLU of 4 x 64 hidden units: one exp and one
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "3b280a7dd9a439142003123b36e4d48ed07591e493feb641139a54c9a90e0d17"
+TRAFFIC_SHA256 = "88f3df133d32cc5a7e4bdb0e95732844e3672cb3cdf276e04b863d74124f49c3"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36893 * 1024, 1.0 * 71874 * 1024),
     ("project_kernel", 3): (2.0 * 1530043 * 1024, 1.0 * 228711 * 1024),

@@ -368,7 +368,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CellGa
 backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, const float *__restrict__ geom,
                          const ViewProj *__restrict__ vps, int kind, int V, int R, int C, int mz0, int L,
                          float *__restrict__ T) {
-    using Rule = GLRule<Degree<n>::m>;
     constexpr int NB = n + 1;
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
