@@ -136,6 +136,9 @@ def test_degree0_is_chord_length_of_unit_cube():
     assert oracle.footprint(0, w, x) == pytest.approx(inside.sum() * (t[1] - t[0]), abs=1e-5)
 
 
+# quad reports that round-off keeps it from its 1e-13 target on the kinks of
+# the degree-1 integrand; the comparison below asks for 1e-9 only
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
 @pytest.mark.parametrize("n", [1, 2, 3])
 def test_brute_force_adaptive_quadrature(n):
     rng = np.random.default_rng(70 + n)
