@@ -346,20 +346,8 @@ __device__ __forceinline__ void walk_init(Walk<n> &W, const LineD &L, const int 
     if (W.j <= W.j1) W.window();
 }
 
-// The slab walk of one line per lane, with the footprint of each (line,
-// basis) pair it yields taken from the network (EXACT = false: the wave
-// evaluates the 64 pairs of a round on the matrix cores) or from the exact
-// piecewise Gauss-Legendre integral (EXACT = true: each lane on its own).
-// The exact variant is the reference point of the network: the same walk,
-// windows and pair gating, only the footprint differs.
 // The network forward's pairs waiting to be evaluated, a ring of 128 per
 // wave: the five features, the coefficient's index and the owning lane.
-// Each lane walks its own line and appends the pairs it finds; whenever 64
-// are buffered the wave evaluates them, one pair per lane, and adds c times
-// the footprint to the owning lane's sum in LDS (atomic adds within the
-// wave).  Rounds stay full while some lines of the wave are done and others
-// are not (about 6 % empty slots at cone_256 when each lane evaluated its
-// own pairs).
 constexpr int FBUF = 128;
 struct FwdPairBuf {
     float f[5][FBUF];
@@ -367,6 +355,18 @@ struct FwdPairBuf {
     int owner[FBUF];
 };
 
+// The slab walk of one line per lane, with the footprint of each (line,
+// basis) pair it yields taken from the network (EXACT = false) or from the
+// exact piecewise Gauss-Legendre integral (EXACT = true: every round each
+// lane evaluates its own next pair).  The exact variant is the reference
+// point of the network: the same walk, windows and pair gating, only the
+// footprint differs.  In the network variant each lane appends the pairs it
+// finds to its wave's ring; whenever 64 are buffered the wave evaluates
+// them on the matrix cores, one pair per lane, and adds c times the
+// footprint to the owning lane's sum in LDS (atomic adds within the wave),
+// so rounds stay full while some lines of the wave are done and others are
+// not (about 6 % empty slots at cone_256 when each lane evaluated its own
+// pairs).
 template <int n, bool EXACT>
 __device__ __forceinline__ void project_walk(const float *__restrict__ c, int N0, int N1, int N2,
                                              const float *__restrict__ geom, int kind, int V, int R, int C,
