@@ -60,7 +60,9 @@
 extern "C" {
 #endif
 
-#define SS_ABI_VERSION 1
+/* 1: first release; 2: adds SS_FORM_QUAD_PAIR_FP32, ss_project_noalloc and
+ * ss_set_scratch_limit (calls and arguments of version 1 unchanged). */
+#define SS_ABI_VERSION 2
 
 typedef enum {
     SS_OK = 0,

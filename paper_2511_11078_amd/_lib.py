@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsplinesplat.so")
+ABI_VERSION = 2  # SS_ABI_VERSION of include/splinesplat.h
 
 SS_OK, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EUNSUPPORTED, SS_EBLOB = range(6)
 FORMS = {"quad": 0, "mlp": 1, "pair": 2}
@@ -70,6 +71,9 @@ def load():
     for name in EXPORTED:
         if name != "ss_last_error":
             getattr(lib, name).restype = I
+    if lib.ss_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} reports ABI version {lib.ss_abi_version()}, the binding expects "
+                           f"{ABI_VERSION}: rebuild it with `python -m paper_2511_11078_amd.build`")
     _lib = lib
     return lib
 

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol():
     out = os.popen(f"nm -D --defined-only {_lib.LIB_PATH}").read()
     for name in names:
         assert re.search(rf"\bT {name}\b", out), f"{name} not exported"
-    assert lib.ss_abi_version() == 1
+    assert lib.ss_abi_version() == _lib.ABI_VERSION == 2
 
 
 def test_validation_errors():
