@@ -61,38 +61,42 @@ MLP_FLOPS_PER_PAIR = 2.0 * 3 * 64 * 64 + 2.0 * 5 * 64 + 2.0 * 64   # hidden BF16
 MLP_TRANS_PER_PAIR = 2 * 4 * 64   # SiLU of 4 x 64 hidden units: one exp and one reciprocal each
 
 
-# HBM bytes per launch of the quadrature kernels on cone_256, from rocprofv3
+# HBM bytes per application (forward or adjoint: the launches of each kernel
+# summed; the cubic forward launches project_kernel twice, once per copy of
+# the coefficients) of the quadrature kernels on cone_256, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
 # counters read for a plain 256 MiB device copy (x2.000 and x1.000); see
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "88f3df133d32cc5a7e4bdb0e95732844e3672cb3cdf276e04b863d74124f49c3"
-TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per launch, cone_256
-    ("pad_volume_kernel", 3): (2.0 * 36893 * 1024, 1.0 * 71874 * 1024),
-    ("project_kernel", 3): (2.0 * 1530043 * 1024, 1.0 * 228711 * 1024),
-    ("backproject_cells_kernel", 3): (2.0 * 3020361 * 1024, 1.0 * 5435998 * 1024),
-    ("cells_to_coeffs_kernel", 3): (2.0 * 2469549 * 1024, 1.0 * 65536 * 1024),
+TRAFFIC_SHA256 = "0c6097d602982d1160cb3abc0e04c5bb64eee00a5550ad002af7b66361f64ae6"
+TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per application, cone_256
+    ("pad_volume_kernel", 3): (2.0 * 36897 * 1024, 1.0 * 71874 * 1024),
+    ("pad_volume_yfast_kernel", 3): (2.0 * 65553 * 1024, 1.0 * 72218 * 1024),
+    ("project_kernel", 3): (2.0 * (1295830 + 1045866) * 1024, 1.0 * (147137 + 94671) * 1024),  # two launches
+    ("backproject_cells_kernel", 3): (2.0 * 3023533 * 1024, 1.0 * 5398899 * 1024),
+    ("cells_to_coeffs_kernel", 3): (2.0 * 2481303 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36895 * 1024, 1.0 * 67084 * 1024),
-    ("project_kernel", 0): (2.0 * 1069215 * 1024, 1.0 * 254652 * 1024),
-    ("backproject_cells_kernel", 0): (2.0 * 1250446 * 1024, 1.0 * 67074 * 1024),
-    ("cells_to_coeffs_kernel", 0): (2.0 * 32787 * 1024, 1.0 * 65536 * 1024),
+    ("project_kernel", 0): (2.0 * 1069235 * 1024, 1.0 * 254618 * 1024),
+    ("backproject_cells_kernel", 0): (2.0 * 1260068 * 1024, 1.0 * 67106 * 1024),
+    ("cells_to_coeffs_kernel", 0): (2.0 * 32785 * 1024, 1.0 * 65536 * 1024),
 }
 
 
-# L2 -> L1 fill bytes per launch on cone_256: rocprofv3 TCP_TCC_READ_REQ_sum
+# L2 -> L1 fill bytes per application on cone_256: rocprofv3 TCP_TCC_READ_REQ_sum
 # times 128 bytes, the request size a plain device copy shows (1 GiB read in
 # 8,388,608 requests); same source check as the HBM bytes.  The L2 peak is
 # derived from the unit counts: 8 XCDs x 16 channels x 128 bytes per clock
 # at 2.4 GHz; the best L2-read rate measured by peaks_probe.hip is below it.
-L2_FILL_BYTES = {  # (kernel, degree) -> bytes per launch, cone_256
+L2_FILL_BYTES = {  # (kernel, degree) -> bytes per application, cone_256
     ("pad_volume_kernel", 3): 128.0 * 589824,
-    ("project_kernel", 3): 128.0 * 23811369747,
-    ("backproject_cells_kernel", 3): 128.0 * 210756872,
-    ("cells_to_coeffs_kernel", 3): 128.0 * 45826707,
+    ("pad_volume_yfast_kernel", 3): 128.0 * 1048576,
+    ("project_kernel", 3): 128.0 * (12960493046 + 6705862807),  # two launches
+    ("backproject_cells_kernel", 3): 128.0 * 210753563,
+    ("cells_to_coeffs_kernel", 3): 128.0 * 45215857,
     ("pad_volume_kernel", 0): 128.0 * 589824,
-    ("project_kernel", 0): 128.0 * 5703180801,
-    ("backproject_cells_kernel", 0): 128.0 * 194943899,
+    ("project_kernel", 0): 128.0 * 5704423358,
+    ("backproject_cells_kernel", 0): 128.0 * 194942051,
     ("cells_to_coeffs_kernel", 0): 128.0 * 524288,
 }
 PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
@@ -110,8 +114,9 @@ def _sources_match() -> bool:
 
 
 def measured_traffic(kernels, degree: int, workload: str):
-    """HBM bytes of one launch of the named kernels (summed), or None when
-    they were not measured for this workload and these sources."""
+    """HBM bytes of one application (forward or adjoint) of the named kernels
+    (summed), or None when they were not measured for this workload and these
+    sources."""
     if workload != "cone_256" or any((k, degree) not in TRAFFIC_BYTES for k in kernels):
         return None
     if not _sources_match():
@@ -120,8 +125,8 @@ def measured_traffic(kernels, degree: int, workload: str):
 
 
 def measured_l2(kernels, degree: int, workload: str, ms: float):
-    """L2 -> L1 fill rate of one launch of the named kernels against the L2
-    peak, or None when not measured for this workload and these sources."""
+    """L2 -> L1 fill rate of one application of the named kernels against the
+    L2 peak, or None when not measured for this workload and these sources."""
     if workload != "cone_256" or any((k, degree) not in L2_FILL_BYTES for k in kernels):
         return None
     if not _sources_match():
@@ -375,8 +380,13 @@ def main():
                 fl_f = R * cells_per_ray * fwd_unit_flops(n)
                 fl_a = (R * cells_per_ray * adj_unit_flops(n) + ncells * adj_cell_flops(n)
                         + nb3 * float(np.prod(dims)))
+                # degree 3 walks each view in one of two copies of the
+                # coefficients (x or y fastest): two pads, two launches
+                fwd_name = (f"pad_volume_kernel + pad_volume_yfast_kernel + project_kernel<{n}> "
+                            f"(knot-cell walk, two launches)" if n == 3 else
+                            f"pad_volume_kernel + project_kernel<{n}> (knot-cell walk)")
                 for name, ms, fl, unit in (
-                        (f"pad_volume_kernel + project_kernel<{n}> (knot-cell walk)", fwd_ms, fl_f,
+                        (fwd_name, fwd_ms, fl_f,
                          f"{fwd_unit_flops(n):.0f} flop per (line, cell) x {cells_per_ray:.1f} cells/line"),
                         (f"backproject_cells_kernel<{n}> + cells_to_coeffs_kernel<{n}> (knot-cell gather)",
                          adj_ms, fl_a,

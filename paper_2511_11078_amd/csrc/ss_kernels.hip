@@ -33,6 +33,54 @@ __global__ void __launch_bounds__(256) pad_volume_kernel(const float *__restrict
     }
 }
 
+// The same copy with x and y exchanged (y fastest: element (x, y, z) at
+// ((z + P) (N0 + 2P) + x + P) (N1 + 2P) + y + P), for the views the forward
+// walks in that order; each block transposes a 32 x 32 (x, y) tile of one
+// z layer through LDS.
+constexpr int PAD_T = 32;
+__global__ void __launch_bounds__(256) pad_volume_yfast_kernel(const float *__restrict__ c, int N0, int N1, int N2,
+                                                               int P, float *__restrict__ out) {
+    __shared__ float tile[PAD_T][PAD_T + 1];  // [y][x] of the tile
+    const int Sx = N0 + 2 * P, Sy = N1 + 2 * P;
+    const int tiles_x = (Sx + PAD_T - 1) / PAD_T, tiles_y = (Sy + PAD_T - 1) / PAD_T;
+    const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y;
+    const int zp = blockIdx.x / (tiles_x * tiles_y);  // padded z layer
+    const int z = zp - P;
+    const int tx = threadIdx.x % PAD_T, ty = threadIdx.x / PAD_T;  // 32 x 8
+#pragma unroll
+    for (int k = 0; k < PAD_T; k += 8) {
+        const int x = bx * PAD_T + tx - P, yy = by * PAD_T + ty + k - P;
+        const bool in = x >= 0 && x < N0 && yy >= 0 && yy < N1 && z >= 0 && z < N2;
+        tile[ty + k][tx] = in ? c[((int64_t)z * N1 + yy) * N0 + x] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PAD_T; k += 8) {
+        const int xp = bx * PAD_T + ty + k, yp = by * PAD_T + tx;
+        if (xp < Sx && yp < Sy) out[((int64_t)zp * Sx + xp) * Sy + yp] = tile[tx][ty + k];
+    }
+}
+
+// Whether the cubic forward walks view e in the y-fastest copy.  Measured
+// per 5-degree range of circular cone trajectories (256^3 and 512^3): with
+// phi the angle between the view's central ray and its dominant horizontal
+// axis, rows along the minor horizontal axis are faster for phi < 15
+// degrees and rows along the dominant axis for 15 <= phi < 35; beyond, and
+// for views whose central ray is mostly along z, the x-fastest copy.  Both
+// copies hold the same values, so the choice changes only the FP32
+// rounding order of the contraction, not what is computed.
+__device__ __forceinline__ bool view_walks_yfast(const float *__restrict__ e, int kind) {
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = kind != 0 ? e[3 + k] - e[k] : e[k];  // cone: source -> detector centre
+    const float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    const float hi = fmaxf(ax, ay), lo = fminf(ax, ay);
+    if (!(az < hi)) return false;
+    const float s = lo / hi;                        // tan(phi)
+    constexpr float T15 = 0.26794919f, T35 = 0.70020754f;
+    return ax >= ay ? s < T15 : (s >= T15 && s < T35);
+}
+
 // ---------------------------------------------------------------------------
 // Forward, quadrature form: cell walk.  The footprint of a basis is the sum,
 // over the knot cells its support spans, of the Gauss-Legendre integral of
@@ -44,10 +92,14 @@ __global__ void __launch_bounds__(256) pad_volume_kernel(const float *__restrict
 // same Gauss-Legendre terms as the slab-by-slab per-basis sum, evaluated
 // with the node positions and per-axis weights shared by the (n+1)^3 bases.
 // ---------------------------------------------------------------------------
+// Launched once per copy: with yfast = 0 on the x-fastest copy for the views
+// that walk it, with yfast = 1 on the y-fastest copy for the others (blocks
+// of the other views return at once); the walk then runs with x and y
+// exchanged.
 template <int n>
 __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict__ cp, int N0, int N1, int N2,
                                                       const float *__restrict__ geom, int kind, int V, int R,
-                                                      int C, float *__restrict__ y) {
+                                                      int C, float *__restrict__ y, int yfast) {
     using Rule = GLRule<Degree<n>::m>;
     constexpr int NB = n + 1;
     constexpr double h = (double)Degree<n>::h;
@@ -56,13 +108,20 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
     int v, tr, tc;
     if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot
+    if (v < V && (n == 3 && view_walks_yfast(geom + 12 * v, kind)) != (yfast != 0)) return;  // the other copy's view
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = tr * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int i = tc * 16 + (wave & 1) * 8 + (lane & 7);
     if (v >= V || j >= R || i >= C) return;
-    const int N[3] = {N0, N1, N2};
+    // the walk runs in the copy's axis order: (x, y, z), or (y, x, z)
+    const int N[3] = {yfast ? N1 : N0, yfast ? N0 : N1, N2};
     const double centre[3] = {0.0, 0.0, 0.0};
-    const LineD L = make_line(geom + 12 * v, kind, R, C, j, i, centre);
+    LineD L = make_line(geom + 12 * v, kind, R, C, j, i, centre);
+    if (yfast) {
+        const double a0 = L.a[0], w0 = L.w[0];
+        L.a[0] = L.a[1]; L.a[1] = a0;
+        L.w[0] = L.w[1]; L.w[1] = w0;
+    }
     float acc = 0.0f;
     if (L.ok) {
         // index coordinates z = x - o, o = -(N - 1)/2
@@ -109,8 +168,8 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
             }
             // zero-padded copy of the coefficients (FWD_PAD(n) layers per side)
             constexpr int P = FWD_PAD(n);
-            const int64_t s1 = N0 + 2 * P, s2 = (int64_t)(N0 + 2 * P) * (N1 + 2 * P);
-            const int hi0 = N0 - 1 + P - n, hi1 = N1 - 1 + P - n, hi2 = N2 - 1 + P - n;
+            const int64_t s1 = N[0] + 2 * P, s2 = (int64_t)(N[0] + 2 * P) * (N[1] + 2 * P);
+            const int hi0 = N[0] - 1 + P - n, hi1 = N[1] - 1 + P - n, hi2 = N[2] - 1 + P - n;
             double tc = t0;
             // every step moves one axis to its next knot plane: the walk ends
             // after at most sum_k (N_k + 2h + 2) steps
@@ -746,7 +805,18 @@ static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     // walk (one coefficient per cell) runs best at full occupancy.
     constexpr int FWD_IDLE_LDS = n == 0 ? 0 : 50 * 1024;  // 3 x 50 KiB of the CU's 160 KiB
     hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), FWD_IDLE_LDS, st, a.scratch, a.N[0], a.N[1],
-                       a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino);
+                       a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino, 0);
+    if constexpr (n == 3) {
+        // the views that walk the y-fastest copy: the same scratch, rewritten
+        // after the first launch (stream order)
+        const int64_t yb = (int64_t)((a.N[0] + 2 * P + PAD_T - 1) / PAD_T) * ((a.N[1] + 2 * P + PAD_T - 1) / PAD_T) *
+                           (a.N[2] + 2 * P);
+        if (yb > INT32_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(pad_volume_yfast_kernel, dim3((unsigned)yb), dim3(256), 0, st, a.coeffs, a.N[0], a.N[1],
+                           a.N[2], P, a.scratch);
+        hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), FWD_IDLE_LDS, st, a.scratch, a.N[0], a.N[1],
+                           a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino, 1);
+    }
     return hipGetLastError();
 }
 
