@@ -69,7 +69,7 @@ MLP_TRANS_PER_PAIR = 2 * 4 * 64   # SiLU of 4 x 64 hidden units: one exp and one
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "0c6097d602982d1160cb3abc0e04c5bb64eee00a5550ad002af7b66361f64ae6"
+TRAFFIC_SHA256 = "cbda849d4b6bc1f236e642d75ddfb4f328a13af9e1514310463b66443937d47e"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per application, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36897 * 1024, 1.0 * 71874 * 1024),
     ("pad_volume_yfast_kernel", 3): (2.0 * 65553 * 1024, 1.0 * 72218 * 1024),

@@ -61,8 +61,9 @@ __global__ void __launch_bounds__(256) pad_volume_yfast_kernel(const float *__re
     }
 }
 
-// Whether the cubic forward walks view e in the y-fastest copy.  Measured
-// per 5-degree range of circular cone trajectories (256^3 and 512^3): with
+// Whether the forward (degrees 1 to 3) walks view e in the y-fastest copy.
+// Measured per 5-degree range of circular cone trajectories (256^3 and
+// 512^3, degree 3; degrees 2 and 1 gain as much from it): with
 // phi the angle between the view's central ray and its dominant horizontal
 // axis, rows along the minor horizontal axis are faster for phi < 15
 // degrees and rows along the dominant axis for 15 <= phi < 35; beyond, and
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256, 4) project_kernel(const float *__restrict
     const int tR = (R + 15) / 16, tC = (C + 15) / 16;
     int v, tr, tc;
     if (!fwd_block_tile(V, tR, tC, v, tr, tc)) return;  // padding slot
-    if (v < V && (n == 3 && view_walks_yfast(geom + 12 * v, kind)) != (yfast != 0)) return;  // the other copy's view
+    if (v < V && (n >= 1 && view_walks_yfast(geom + 12 * v, kind)) != (yfast != 0)) return;  // the other copy's view
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = tr * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int i = tc * 16 + (wave & 1) * 8 + (lane & 7);
@@ -806,9 +807,10 @@ static hipError_t launch_project_n(const LaunchArgs &a, hipStream_t st) {
     constexpr int FWD_IDLE_LDS = n == 0 ? 0 : 50 * 1024;  // 3 x 50 KiB of the CU's 160 KiB
     hipLaunchKernelGGL(project_kernel<n>, dim3(nb), dim3(256), FWD_IDLE_LDS, st, a.scratch, a.N[0], a.N[1],
                        a.N[2], a.geom, a.kind, a.V, a.R, a.C, a.sino, 0);
-    if constexpr (n == 3) {
+    if constexpr (n >= 1) {
         // the views that walk the y-fastest copy: the same scratch, rewritten
-        // after the first launch (stream order)
+        // after the first launch (stream order); the degree-0 walk, bound by
+        // L2 refills rather than by its arithmetic, keeps one copy
         const int64_t yb = (int64_t)((a.N[0] + 2 * P + PAD_T - 1) / PAD_T) * ((a.N[1] + 2 * P + PAD_T - 1) / PAD_T) *
                            (a.N[2] + 2 * P);
         if (yb > INT32_MAX) return hipErrorInvalidValue;
