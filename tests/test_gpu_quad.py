@@ -167,6 +167,41 @@ def test_backproject_all_coefficients(ctxs, n, kind):
     assert e <= (TOL if n > 0 else 1e-4)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_forward_copy_choice_by_view_angle(ctxs, n):
+    """The forward walks each view in the x- or the y-fastest copy of the
+    coefficients, chosen from the angle between the view's central ray and
+    its dominant horizontal axis (thresholds 15 and 35 degrees): views on
+    both sides of every threshold, in several quadrants, each against the
+    oracle; and the allocation-free forward, which runs the same two
+    launches, equal bit for bit."""
+    say(f"forward copy choice n={n}")
+    dims = (13, 11, 9)
+    angles = [2, 14, 16, 34, 36, 54, 56, 74, 76, 88, 106, 196]
+    one = [synth.cone_circular_geometry(1, 20, 22, src_radius=40.0, src_det=60.0, angle0=np.deg2rad(a))
+           for a in angles]
+    geom = synth.Geometry("cone", len(angles), 20, 22, np.concatenate([g.vecs for g in one]))
+
+    def walks_yfast(e):  # the kernel's rule, restated to check that both copies are used
+        ax, ay, az = np.abs(e[3:6].astype(np.float64) - e[0:3])
+        hi, lo = max(ax, ay), min(ax, ay)
+        if not az < hi:
+            return False
+        t = lo / hi
+        return t < np.tan(np.deg2rad(15)) if ax >= ay else np.tan(np.deg2rad(15)) <= t < np.tan(np.deg2rad(35))
+
+    side = [walks_yfast(e) for e in geom.vecs]
+    assert any(side) and not all(side)
+    c = np.random.default_rng(260 + n).uniform(0.0, 1.0, dims[::-1]).astype(np.float32)
+    got = to_np(ctxs[n].project(to_gpu(c), geom))
+    want = oracle.project(c, geom, n).reshape(got.shape)
+    errs = [rel_l2(got[k], want[k]) for k in range(len(angles))]
+    say("  per view rel-L2 " + " ".join(f"{a}:{e:.1e}" for a, e in zip(angles, errs)))
+    assert max(errs) <= TOL
+    from paper_2511_11078_amd.ops import project_noalloc
+    assert np.array_equal(to_np(project_noalloc(to_gpu(c), geom, degree=n)), got)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 3])
 def test_backproject_z_chunks_match_one_pass(n):
     """A scratch limit below the knot-cell table splits the adjoint into
