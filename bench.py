@@ -69,12 +69,12 @@ MLP_TRANS_PER_PAIR = 2 * 4 * 64   # SiLU of 4 x 64 hidden units: one exp and one
 # profiles/cone256_traffic_counters.md.  Valid only for the kernel sources they
 # were measured on (SHA-256 over QUAD_SOURCES); otherwise reported as null.
 QUAD_SOURCES = ["csrc/ss_kernels.hip", "csrc/ss_math.hpp", "csrc/ss_traverse.hpp", "csrc/ss_kernels.hpp"]
-TRAFFIC_SHA256 = "cbda849d4b6bc1f236e642d75ddfb4f328a13af9e1514310463b66443937d47e"
+TRAFFIC_SHA256 = "369c6360167dcf2aa49bd385ba21713a13c9bf62f635122478f66696ae4d78ea"
 TRAFFIC_BYTES = {  # (kernel, degree) -> (read bytes, written bytes) per application, cone_256
     ("pad_volume_kernel", 3): (2.0 * 36897 * 1024, 1.0 * 71874 * 1024),
     ("pad_volume_yfast_kernel", 3): (2.0 * 65553 * 1024, 1.0 * 72218 * 1024),
     ("project_kernel", 3): (2.0 * (1295830 + 1045866) * 1024, 1.0 * (147137 + 94671) * 1024),  # two launches
-    ("backproject_cells_kernel", 3): (2.0 * 3023533 * 1024, 1.0 * 5398899 * 1024),
+    ("backproject_cells_kernel", 3): (2.0 * 3007007 * 1024, 1.0 * 5412897 * 1024),
     ("cells_to_coeffs_kernel", 3): (2.0 * 2481303 * 1024, 1.0 * 65536 * 1024),
     ("pad_volume_kernel", 0): (2.0 * 36895 * 1024, 1.0 * 67084 * 1024),
     ("project_kernel", 0): (2.0 * 1069235 * 1024, 1.0 * 254618 * 1024),
@@ -92,7 +92,7 @@ L2_FILL_BYTES = {  # (kernel, degree) -> bytes per application, cone_256
     ("pad_volume_kernel", 3): 128.0 * 589824,
     ("pad_volume_yfast_kernel", 3): 128.0 * 1048576,
     ("project_kernel", 3): 128.0 * (12960493046 + 6705862807),  # two launches
-    ("backproject_cells_kernel", 3): 128.0 * 210753563,
+    ("backproject_cells_kernel", 3): 128.0 * 210638300,
     ("cells_to_coeffs_kernel", 3): 128.0 * 45215857,
     ("pad_volume_kernel", 0): 128.0 * 589824,
     ("project_kernel", 0): 128.0 * 5704423358,

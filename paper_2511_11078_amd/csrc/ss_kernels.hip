@@ -295,6 +295,8 @@ template <int n> struct CellGather {
     static constexpr int cap = (lds - fixed) / 40 / 16 * 16;  // lines in the LDS table (40 bytes each)
     static constexpr int half = cap / 2;
     static constexpr int views_per_half = n == 3 ? 5 : 3;
+    // wave priority while a block sets up a view (0: the default throughout)
+    static constexpr int setup_prio = n == 0 ? 0 : 2;
 };
 constexpr float PIX_MARGIN = 1.0e-3f;           // pixels; covers FP32 rounding of the corner table
 
@@ -432,6 +434,19 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     constexpr int qoff = CellBasis<n>::qoff;
     constexpr double kap = (double)Degree<n>::kap;
     constexpr int CRAY_HALF = CellGather<n>::half, VIEWS_PER_HALF = CellGather<n>::views_per_half;
+    // A view's set-up (corner table, rectangles, line table, queueing) is
+    // short dependent chains ending in a barrier; the integration is long
+    // runs of independent FMAs.  Raising a wave's priority for the set-up
+    // lets each block reach its barrier sooner while the other blocks on the
+    // CU keep the FMA pipes busy (degrees 1-3; the degree-0 kernel, whose
+    // integration is short, runs faster without).
+    constexpr int PRIO = CellGather<n>::setup_prio;
+    const auto prio_setup = [] {
+        if constexpr (PRIO > 0) __builtin_amdgcn_s_setprio(PRIO);
+    };
+    const auto prio_integrate = [] {
+        if constexpr (PRIO > 0) __builtin_amdgcn_s_setprio(0);
+    };
     static_assert(sizeof(CellRay) == 40, "line record size assumed by the LDS budget");
     __shared__ CellRay rays[CellGather<n>::cap];
     __shared__ unsigned short hitq[HITQ_CAP * 256];  // per-thread queue of candidate table indices
@@ -498,6 +513,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
     __syncthreads();
 
     for (int v = 0; v < V; ++v) {
+        prio_setup();
         const float *e = geom + 12 * v;
         const float2 *cornerv = corner[v & 1];
         const bool anybad = badview[v & 1] == v + 1;
@@ -542,6 +558,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                         // same rounds (the wave runs as many rounds as its
                         // lane with the most entries in the other half)
                         if (other_filled) {
+                            prio_integrate();
                             int K = nolder;
 #pragma unroll
                             for (int m = 32; m >= 1; m >>= 1) K = max(K, __shfl_xor(K, m));
@@ -555,6 +572,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
                             }
                             count -= npop;
                             __syncthreads();  // no wave reads the other half any more
+                            prio_setup();
                         }
                         nolder = count;  // every queued entry is now in the older half
                         half ^= 1;
@@ -611,6 +629,7 @@ backproject_cells_kernel(const float *__restrict__ y, int N0, int N1, int N2, co
         }
         if (!barrier) __syncthreads();
     }
+    prio_integrate();
     int idx = hitq[qhead];
     for (int k = 0; k < count; ++k) {
         qhead = (qhead + 256) & QMASK;
